@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test names what fixes the expected value: exact rational arithmetic,
+integer arithmetic, closed forms, invariants of the GEMM definition, or a
+library conversion routine.  A plausible mistake in the oracle (a dropped
+term, a wrong sign or index, a transposed operand, alpha/beta swapped, beta
+applied when zero, a wrong rounding tie) fails at least one of them.
+"""
+from fractions import Fraction
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import seeded_inputs as si
+
+
+def _stored(logical, trans):
+    buf, ld = si.store(logical, trans)
+    return buf, ld
+
+
+def _run(opA, opB, tA="N", tB="N", alpha=1.0, beta=0.0, C0=None, threads=None):
+    M, K = opA.shape
+    N = opB.shape[1]
+    A, lda = _stored(opA, tA)
+    B, ldb = _stored(opB, tB)
+    return oracle.gemm(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, N, threads=threads)
+
+
+# ---------------------------------------------------------------- GEMM ----
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (2, 3, 4), (5, 4, 3), (3, 5, 6), (6, 6, 6), (4, 1, 5)])
+@pytest.mark.parametrize("tA,tB", [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")])
+def test_gemm_exact_rational_dyadic(M, N, K, tA, tB):
+    """Short dyadic inputs: every product and partial sum is exact, so the
+    oracle must equal the exact rational result of the definition."""
+    opA = si.dyadic((M, K), 11 + M)
+    opB = si.dyadic((K, N), 12 + N)
+    C0 = si.dyadic((M, N), 13 + K)
+    alpha, beta = 1.5, -0.75
+    C, D = _run(opA, opB, tA, tB, alpha, beta, C0)
+    for i in range(M):
+        for j in range(N):
+            s = sum(Fraction(float(opA[i, k])) * Fraction(float(opB[k, j])) for k in range(K))
+            d = sum(abs(Fraction(float(opA[i, k])) * Fraction(float(opB[k, j]))) for k in range(K))
+            exact = Fraction(alpha) * s + Fraction(beta) * Fraction(float(C0[i, j]))
+            dexact = Fraction(abs(alpha)) * d + Fraction(abs(beta)) * abs(Fraction(float(C0[i, j])))
+            assert Fraction(C[i, j]) == exact
+            assert Fraction(D[i, j]) == dexact
+
+
+@pytest.mark.parametrize("M,N,K", [(3, 4, 5), (6, 2, 6), (5, 5, 1)])
+def test_gemm_random_float32_within_fp64_bound(M, N, K):
+    """Random float32 inputs: the oracle lies within the FP64 summation bound
+    of the exact result (each product is exact; at most K roundings)."""
+    opA = si.uniform((M, K), 21)
+    opB = si.uniform((K, N), 22)
+    C0 = si.uniform((M, N), 23)
+    alpha, beta = 1.5, 0.5
+    C, _ = _run(opA, opB, alpha=alpha, beta=beta, C0=C0)
+    u = Fraction(1, 2 ** 53)
+    for i in range(M):
+        for j in range(N):
+            terms = [Fraction(float(opA[i, k])) * Fraction(float(opB[k, j])) for k in range(K)]
+            exact = Fraction(alpha) * sum(terms) + Fraction(beta) * Fraction(float(C0[i, j]))
+            bound = (K + 3) * u * (Fraction(alpha) * sum(abs(t) for t in terms)
+                                   + Fraction(beta) * abs(Fraction(float(C0[i, j])))) * 2
+            assert abs(Fraction(C[i, j]) - exact) <= bound
+
+
+def test_gemm_integer_exact_vs_int64_matmul():
+    """Integer entries: the FP64 result is exact and equals int64 arithmetic."""
+    opA = si.integers((37, 53), 31)
+    opB = si.integers((53, 29), 32)
+    C0 = si.integers((37, 29), 33)
+    C, D = _run(opA, opB, alpha=3.0, beta=-2.0, C0=C0)
+    ref = 3 * (opA.astype(np.int64) @ opB.astype(np.int64)) - 2 * C0.astype(np.int64)
+    dref = 3 * (np.abs(opA).astype(np.int64) @ np.abs(opB).astype(np.int64)) + 2 * np.abs(C0).astype(np.int64)
+    assert np.array_equal(C, ref.astype(np.float64))
+    assert np.array_equal(D, dref.astype(np.float64))
+
+
+def test_gemm_layouts_bitwise_identical():
+    """NN/NT/TN/TT of the same logical operands must give identical bits:
+    the transpose only changes how elements are fetched."""
+    opA = si.uniform((19, 23), 41)
+    opB = si.uniform((23, 17), 42)
+    C0 = si.uniform((19, 17), 43)
+    outs = [_run(opA, opB, tA, tB, 1.5, 0.5, C0)[0] for tA in "NT" for tB in "NT"]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    # lower-case and 'C' (conjugate == transpose for real data) are accepted
+    Cc = _run(opA, opB, "c", "n", 1.5, 0.5, C0)[0]
+    assert np.array_equal(Cc, outs[0])
+
+
+def test_gemm_padded_leading_dimension():
+    """lda/ldb larger than the row length: the padding (NaN) is never read."""
+    opA = si.uniform((7, 9), 51)
+    opB = si.uniform((9, 5), 52)
+    A, lda = si.store(opA, "T", ld=13)
+    B, ldb = si.store(opB, "N", ld=11)
+    C, _ = oracle.gemm("T", "N", 7, 5, 9, 1.0, A, lda, B, ldb)
+    C2, _ = _run(opA, opB)
+    assert np.array_equal(C, C2)
+    assert not np.isnan(C).any()
+
+
+def test_gemm_column_major_operand_swap_identity():
+    """A column-major GEMM is the row-major GEMM of the swapped operands:
+    colmajor(C) = A B  <=>  rowmajor(C^T) = B^T A^T."""
+    opA = si.uniform((6, 8), 61)
+    opB = si.uniform((8, 4), 62)
+    # column-major storage of opA is the row-major storage of opA^T
+    A_cm = np.ascontiguousarray(opA.T).reshape(-1)
+    B_cm = np.ascontiguousarray(opB.T).reshape(-1)
+    # row-major call computing C^T = opB^T opA^T, with B_cm as the first operand ('N')
+    Ct, _ = oracle.gemm("N", "N", 4, 6, 8, 1.0, B_cm, 8, A_cm, 6)
+    C, _ = _run(opA, opB)
+    assert np.array_equal(Ct.T, C)
+
+
+@pytest.mark.parametrize("tA,tB", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
+def test_gemm_identity_and_permutation(tA, tB):
+    """A = I gives alpha*B + beta*C0; A = P gives the permuted rows of B."""
+    n = 11
+    B = si.uniform((n, 7), 71)
+    C0 = si.uniform((n, 7), 72)
+    C, _ = _run(np.eye(n, dtype=np.float32), B, tA, tB, 2.0, 0.5, C0)
+    assert np.array_equal(C, 2.0 * B.astype(np.float64) + 0.5 * C0.astype(np.float64))
+    perm = np.random.default_rng(73).permutation(n)
+    P = np.eye(n, dtype=np.float32)[perm]
+    C, _ = _run(P, B, tA, tB)
+    assert np.array_equal(C, B[perm].astype(np.float64))
+    # permutation on the right permutes columns
+    Q = np.eye(7, dtype=np.float32)[np.random.default_rng(74).permutation(7)]
+    C, _ = _run(B, Q, tA, tB)
+    assert np.array_equal(C, (B @ Q).astype(np.float64))
+
+
+def test_gemm_ones_closed_form():
+    """All-ones A and B: every entry is alpha*K + beta*C0."""
+    M, N, K = 9, 10, 77
+    C0 = si.integers((M, N), 81)
+    C, D = _run(np.ones((M, K), np.float32), np.ones((K, N), np.float32), alpha=1.5, beta=0.5, C0=C0)
+    assert np.array_equal(C, 1.5 * K + 0.5 * C0.astype(np.float64))
+    assert np.array_equal(D, 1.5 * K + 0.5 * np.abs(C0).astype(np.float64))
+
+
+def test_gemm_alpha_beta_not_swapped_and_signs():
+    """Distinguish alpha from beta and both signs with a 1x1x1 problem."""
+    for alpha, beta in [(2.0, 3.0), (-2.0, 3.0), (2.0, -3.0), (0.5, 0.25)]:
+        C, D = oracle.gemm("N", "N", 1, 1, 1, alpha, np.array([5.0]), 1, np.array([7.0]), 1,
+                           beta, np.array([11.0]), 1)
+        assert C[0, 0] == alpha * 35.0 + beta * 11.0
+        assert D[0, 0] == abs(alpha) * 35.0 + abs(beta) * 11.0
+
+
+def test_gemm_special_values():
+    """BLAS readings: beta = 0 never reads C0; alpha = 0 or K = 0 give beta*C0;
+    M = 0 or N = 0 is empty; a NaN in A only touches its own row."""
+    M, N, K = 5, 6, 7
+    opA = si.uniform((M, K), 91)
+    opB = si.uniform((K, N), 92)
+    C0 = si.uniform((M, N), 93)
+    nanC = np.full((M, N), np.nan, np.float32)
+    C, _ = _run(opA, opB, beta=0.0, C0=nanC)
+    assert not np.isnan(C).any()
+    A_nan = opA.copy()
+    A_nan[2, 3] = np.nan
+    C, _ = _run(A_nan, opB, alpha=0.0, beta=0.5, C0=C0)
+    assert np.array_equal(C, 0.5 * C0.astype(np.float64))
+    C, _ = oracle.gemm("N", "N", M, N, 0, 1.0, np.zeros(1), 1, np.zeros(1), N, 0.5, C0, N)
+    assert np.array_equal(C, 0.5 * C0.astype(np.float64))
+    C, _ = oracle.gemm("N", "N", M, N, 0, 1.0, np.zeros(1), 1, np.zeros(1), N, 0.0, nanC, N)
+    assert np.array_equal(C, np.zeros((M, N)))
+    C, _ = oracle.gemm("N", "N", 0, N, K, 1.0, np.zeros(1), K, opB, N)
+    assert C.shape == (0, N)
+    C, _ = _run(A_nan, opB)
+    assert np.isnan(C[2]).all()
+    assert not np.isnan(np.delete(C, 2, axis=0)).any()
+    A_inf = opA.copy()
+    A_inf[1, 0] = np.inf
+    C, _ = _run(A_inf, np.abs(opB) + 1)
+    assert np.isinf(C[1]).all() and not np.isinf(np.delete(C, 1, axis=0)).any()
+
+
+def test_gemm_thread_count_invariant():
+    opA = si.uniform((33, 41), 101)
+    opB = si.uniform((41, 27), 102)
+    C1, D1 = _run(opA, opB, threads=1)
+    C8, D8 = _run(opA, opB, threads=8)
+    assert np.array_equal(C1, C8) and np.array_equal(D1, D8)
+
+
+def test_gemm_entries_match_full():
+    M, N, K = 31, 29, 43
+    for tA, tB in itertools.product("NT", "NT"):
+        opA = si.uniform((M, K), 111)
+        opB = si.uniform((K, N), 112)
+        C0 = si.uniform((M, N), 113)
+        A, lda = si.store(opA, tA)
+        B, ldb = si.store(opB, tB)
+        C, D = oracle.gemm(tA, tB, M, N, K, 1.5, A, lda, B, ldb, 0.5, C0, N)
+        I, J = si.sample_indices(M, N, 100, 114)
+        c, d = oracle.gemm_entries(tA, tB, K, 1.5, A, lda, B, ldb, 0.5, C0, N, I, J)
+        assert np.array_equal(c, C[I, J]) and np.array_equal(d, D[I, J])
+
+
+def test_normalized_error_metric():
+    Cref = np.array([[1.0, 0.0], [2.0, -1.0]])
+    D = np.array([[2.0, 0.0], [4.0, 1.0]])
+    assert oracle.normalized_error(Cref, Cref, D) == 0.0
+    C = Cref + np.array([[0.5, 0.0], [0.0, 0.0]])
+    assert oracle.normalized_error(C, Cref, D) == 0.25
+    C = Cref + np.array([[0.0, 1e-30], [0.0, 0.0]])   # nonzero over a zero denominator
+    assert oracle.normalized_error(C, Cref, D) == float("inf")
+    C = Cref.copy()
+    C[1, 1] = np.nan
+    assert oracle.normalized_error(C, Cref, D) == float("inf")
+
+
+# ------------------------------------------------------------ bfloat16 ----
+
+def _torch_bf16(x):
+    return torch.from_numpy(np.asarray(x, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_bf16_round_matches_library_conversion():
+    """torch's float32 -> bfloat16 cast is round-to-nearest-even."""
+    x = np.concatenate([si.uniform(20000, 121), si.log_uniform_signed(20000, 122, -30, 30),
+                        np.array([0.0, -0.0, 1.0, -1.0, 3.0e38, -3.0e38, 1e-39, -1e-40], np.float32)])
+    # exact ties: low 16 bits == 0x8000, with both even and odd kept parts
+    bits = (np.random.default_rng(123).integers(0x3000, 0x5000, 4000).astype(np.uint32) << 16) | 0x8000
+    ties = bits.view(np.float32)
+    x = np.concatenate([x, ties])
+    assert np.array_equal(oracle.bf16_round(x), _torch_bf16(x))
+
+
+def test_bf16_round_tie_cases_by_hand():
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7 -> even (1)
+    assert oracle.round_to_bits(1 + 2 ** -8, 8, -126) == 1.0
+    # 1 + 3*2^-8 is halfway between 1 + 2^-7 and 1 + 2^-6 -> even (1 + 2^-6)
+    assert oracle.round_to_bits(1 + 3 * 2 ** -8, 8, -126) == 1 + 2 ** -6
+    assert oracle.round_to_bits(-(1 + 3 * 2 ** -8), 8, -126) == -(1 + 2 ** -6)
+    assert oracle.round_to_bits(1 + 2 ** -8 + 2 ** -20, 8, -126) == 1 + 2 ** -7
+
+
+def test_bf16_split_properties():
+    x = np.concatenate([si.uniform(50000, 131), si.log_uniform_signed(50000, 132)]).astype(np.float64)
+    hi, lo = oracle.bf16_split(x)
+    assert np.array_equal(hi, _torch_bf16(x))
+    assert np.array_equal(lo, _torch_bf16((x - hi).astype(np.float32)))
+    # hi + lo carries 16 significant bits: the residual is below 2^-16 |x|
+    assert np.all(np.abs(x - hi - lo) <= 2.0 ** -16 * np.abs(x))
+    # the residual x - hi is exactly representable in float32
+    assert np.array_equal((x - hi).astype(np.float32).astype(np.float64), x - hi)
+
+
+# ------------------------------------------------------------- FP8 E4M3 ---
+
+def _torch_e4m3_table():
+    b = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn)
+    return b.to(torch.float64).numpy()
+
+
+def test_e4m3_decode_matches_library():
+    ours = oracle.e4m3_decode_table()
+    ref = _torch_e4m3_table()
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(ours), nan)
+    assert np.array_equal(ours[~nan], ref[~nan])
+    assert ours[0x7E] == 448.0 and ours[0x08] == 2.0 ** -6 and ours[0x01] == 2.0 ** -9
+
+
+def test_e4m3_encode_roundtrip_all_bytes():
+    table = oracle.e4m3_decode_table()
+    for b in range(256):
+        if np.isnan(table[b]):
+            continue
+        assert oracle.e4m3_encode(table[b]) == b
+
+
+def test_e4m3_round_matches_library():
+    """Below the format maximum, torch's cast to float8_e4m3fn is RNE."""
+    x = np.concatenate([si.uniform(20000, 141, -448, 448), si.log_uniform_signed(20000, 142, -4, 2.6)])
+    x = x[np.abs(x) <= 448]
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    ours = np.array([oracle.e4m3_value(float(v)) for v in x])
+    assert np.array_equal(ours, ref)
+    # saturation (satfinite) above the maximum
+    assert oracle.e4m3_value(500.0) == 448.0 and oracle.e4m3_value(-1e9) == -448.0
+    # ties: 9*2^-? halfway cases, 17/16 is between 1 and 1.125 -> even (1)
+    assert oracle.e4m3_value(1.0625) == 1.0
+    assert oracle.e4m3_value(1.1875) == 1.25
+
+
+def test_tile_scale_by_hand():
+    """s is the smallest power of two with amax <= 448*s."""
+    cases = {448.0: 1.0, 448.5: 2.0, 224.0: 0.5, 224.25: 1.0, 1.0: 2.0 ** -8, 1.75: 2.0 ** -8,
+             1.76: 2.0 ** -7, 8.0: 2.0 ** -5, 0.0: 1.0, 896.0: 2.0, 3.5e-3: 2.0 ** -16, 3.4e-3: 2.0 ** -17}
+    for amax, s in cases.items():
+        assert oracle.tile_scale(amax) == s, amax
+
+
+def test_fp8_quantize_properties():
+    X = si.uniform((300, 260), 151)
+    X[:128, 128:256] *= 1000.0   # one tile with a very different range
+    q, s = oracle.fp8_quantize(X)
+    assert s.shape == (3, 3)
+    deq = oracle.fp8_dequantize(q, s)
+    # each element within half an E4M3 ulp (relative 2^-4) of its value, or of the subnormal quantum
+    tile_s = np.repeat(np.repeat(s.astype(np.float64), 128, 0), 128, 1)[:300, :260]
+    err = np.abs(deq - X)
+    assert np.all(err <= np.maximum(2.0 ** -4 * np.abs(X), 2.0 ** -10 * tile_s))
+    # every tile's max magnitude lands in (224, 448] * s
+    for bi in range(3):
+        for bj in range(3):
+            t = np.abs(X[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128]).max()
+            assert 224 * s[bi, bj] < t <= 448 * s[bi, bj]
+
+
+def test_fp8_quantize_integers_exact():
+    """Integers in [-8, 8] have at most 3 significant bits, so with a power-of-two
+    scale they quantise exactly."""
+    X = si.integers((200, 150), 161)
+    q, s = oracle.fp8_quantize(X)
+    assert np.array_equal(oracle.fp8_dequantize(q, s), X.astype(np.float64))
+
+
+# ------------------------------------------------------------ gradients ---
+
+def test_chain_grads_match_finite_differences():
+    """loss = sum(((X W1) W2) * G) is linear in each single entry, so central
+    differences of the FP64 forward equal the analytic gradient up to rounding."""
+    X = si.uniform((6, 4), 171)
+    W1 = si.uniform((4, 5), 172)
+    W2 = si.uniform((5, 3), 173)
+    G = si.gaussian((6, 3), 174)
+    grads, _ = oracle.chain_grads(X, W1, W2, G)
+
+    def loss(X_, W1_, W2_):
+        _, Y = oracle.chain_forward(X_, W1_, W2_)
+        return float(np.sum(Y * G.astype(np.float64)))
+
+    eps = 1e-3
+    for name, mat in (("dX", X), ("dW1", W1), ("dW2", W2)):
+        for idx in itertools.product(*(range(n) for n in mat.shape)):
+            p = [X.astype(np.float64), W1.astype(np.float64), W2.astype(np.float64)]
+            k = {"dX": 0, "dW1": 1, "dW2": 2}[name]
+            plus = [a.copy() for a in p]
+            minus = [a.copy() for a in p]
+            plus[k][idx] += eps
+            minus[k][idx] -= eps
+            fd = (loss(*plus) - loss(*minus)) / (2 * eps)
+            assert abs(fd - grads[name][idx]) <= 1e-9 * (1 + abs(fd))
+
+
+def test_chain_grads_shapes_and_denominators():
+    X = si.uniform((8, 3), 181)
+    W1 = si.uniform((3, 6), 182)
+    W2 = si.uniform((6, 2), 183)
+    G = si.gaussian((8, 2), 184)
+    g, den = oracle.chain_grads(X, W1, W2, G)
+    assert g["dX"].shape == (8, 3) and g["dW1"].shape == (3, 6) and g["dW2"].shape == (6, 2)
+    for k in g:
+        assert np.all(np.abs(g[k]) <= den[k] * (1 + 1e-12))
