@@ -1,0 +1,120 @@
+/*
+ * mgemm.h -- C ABI of the layered GEMM library for AMD MI355X (gfx950).
+ *
+ * The library computes the GEMM of Kuzma et al., "Fast Matrix Multiplication
+ * via Compiler-only Layered Data Reorganization and Intrinsic Lowering"
+ * (SPE 2023), Section 3 and Algorithm 1:
+ *
+ *     C <- alpha * op(A) * op(B) + beta * C
+ *
+ * with op(X) = X ('N') or X^T ('T'), op(A) M x K, op(B) K x N, C M x N, using
+ * the paper's layers: blocking of C and K into tiles and panels, packing of
+ * the A and B panels into on-chip memory (LDS) in the micro-kernel's access
+ * order, and a micro-kernel lowered to the matrix engine (MFMA).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Storage.  Row-major.  lda/ldb/ldc are row strides in elements.
+ *   transA 'N': A is stored M x K, lda >= max(1, K);  'T': K x M, lda >= max(1, M).
+ *   transB 'N': B is stored K x N, ldb >= max(1, N);  'T': N x K, ldb >= max(1, K).
+ *   ldc >= max(1, N).  'n'/'t' are accepted and 'C'/'c' means 'T' (real data).
+ *   A column-major caller computes gemm(tA, tB, M, N, K, A, lda, B, ldb, C, ldc)
+ *   as the row-major gemm(tB, tA, N, M, K, B, ldb, A, lda, C, ldc).
+ * Ownership.  A, B, C and any workspace are DEVICE pointers owned by the caller.
+ *   The library never allocates or frees device memory in these calls.
+ *   A and B are read only; C is read only when beta != 0 and always written.
+ *   C must not overlap A or B.
+ * Asynchrony.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *   enqueued and the call returns without synchronising; faults inside a
+ *   kernel surface at the caller's next synchronisation.
+ * Quick returns (BLAS).  M == 0 or N == 0: nothing is touched.  K == 0 or
+ *   alpha == 0: C <- beta*C (beta == 0 writes zeros without reading C,
+ *   beta == 1 does nothing); A and B are not read.
+ * Errors.  0 is success.  A negative value -i names the invalid argument by
+ *   its 1-based position in mg_sgemm's signature (BLAS xerbla numbering):
+ *   transA -1, transB -2, M -3, N -4, K -5, A -7, lda -8, B -9, ldb -10,
+ *   C -12, ldc -13.  A NULL pointer is an error only when its matrix has a
+ *   non-zero extent.  All argument errors are detected on the host before any
+ *   device call.  Other codes are the MG_ERR_* values below; a HIP runtime
+ *   error e is returned as MG_ERR_HIP - e.  mg_status_string() describes any
+ *   code.
+ */
+#ifndef MGEMM_H
+#define MGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of a GEMM ("path").  Inputs and outputs are FP32 on every path;
+ * the path only changes what the matrix engine multiplies.  The conversions
+ * happen while packing (Algorithm 1's pack step), so HBM traffic stays FP32. */
+enum mg_path {
+    MG_PATH_FP32 = 0,     /* FP32 x FP32 MFMA, FP32 accumulation                 */
+    MG_PATH_BF16X3 = 1,   /* x = hi + lo (bf16 each); hi*hi + hi*lo + lo*hi on
+                             BF16 MFMA, FP32 accumulation                         */
+    MG_PATH_BF16 = 2,     /* operands rounded to bf16 (nearest-even), FP32 acc.  */
+    MG_PATH_FP8_T128 = 3  /* OCP E4M3 with one power-of-two FP32 scale per
+                             128 x 128 tile of op(A) and op(B), FP32 accumulation */
+};
+
+enum mg_status {
+    MG_OK = 0,
+    MG_ERR_WORKSPACE = -100,    /* workspace missing or smaller than required */
+    MG_ERR_UNSUPPORTED = -101,  /* unknown path or configuration id           */
+    MG_ERR_TOO_LARGE = -102,    /* a dimension exceeds what the kernels index  */
+    MG_ERR_BAD_TABLE = -103,    /* tuning table unreadable or malformed        */
+    MG_ERR_HIP = -1000          /* MG_ERR_HIP - hipError_t                     */
+};
+
+/*
+ * FP32 GEMM on the FP32 matrix cores (the paper's experiments are all FP32
+ * SGEMM, Section 4).  Equivalent to mg_gemm(MG_PATH_FP32, ..., NULL, 0, stream).
+ */
+int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
+             float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+             float beta, float *C, int64_t ldc, void *stream);
+
+/*
+ * GEMM on the given path.  `workspace` (device memory, caller-owned, at least
+ * mg_gemm_workspace_size() bytes, 256-byte aligned) holds the packed FP8
+ * operands on MG_PATH_FP8_T128; the other paths need none (NULL, 0 is fine).
+ * Returns MG_ERR_WORKSPACE if it is too small, MG_ERR_UNSUPPORTED for an
+ * unknown path.
+ */
+int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
+            float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+            float beta, float *C, int64_t ldc,
+            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes mg_gemm needs for this problem (0 when none). */
+size_t mg_gemm_workspace_size(int path, char transA, char transB,
+                              int64_t M, int64_t N, int64_t K);
+
+/*
+ * Tile configurations (the blocking parameters of Section 3.1, Eq. 1-7, as
+ * workgroup tile BM x BN, K-panel depth BK and per-wave micro-tile WM x WN).
+ * mg_num_configs(path) counts the configurations of a path; mg_config_info
+ * fills out[0..5] = {id, BM, BN, BK, WM, WN} and returns 0, or
+ * MG_ERR_UNSUPPORTED for an unknown (path, index).
+ */
+int mg_num_configs(int path);
+int mg_config_info(int path, int index, int *out6);
+
+/*
+ * Force the configuration used for `path` (id from mg_config_info), or -1 to
+ * return to automatic selection.  Process-wide; meant for the autotuner.
+ */
+int mg_force_config(int path, int config_id);
+
+/* Human-readable description of a status code (static storage). */
+const char *mg_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGEMM_H */

@@ -1,0 +1,88 @@
+"""mgemm: the layered GEMM of Kuzma et al. (SPE 2023) on AMD MI355X (gfx950).
+
+The compute runs in the HIP kernels of ``libmgemm.so`` (C ABI in
+``include/mgemm.h``).  This package only marshals torch tensors into device
+pointers, strides and the current HIP stream.  PyTorch provides device memory
+and streams; it computes nothing on the GEMM path.
+"""
+from __future__ import annotations
+
+from . import _native
+from ._native import MgemmError, check, status_string  # noqa: F401
+
+PATHS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+
+
+def _path_id(path) -> int:
+    if isinstance(path, str):
+        try:
+            return PATHS[path]
+        except KeyError:
+            raise ValueError(f"unknown path {path!r}; expected one of {sorted(PATHS)}") from None
+    return int(path)
+
+
+def operand_layout(X):
+    """('N', ld) for a row-major 2-D view, ('T', ld) for a column-major one.
+
+    A contiguous tensor is 'N' with ld = stride(0); the .t() of a contiguous
+    tensor is 'T' with ld = stride(1).  Any other stride pattern is rejected
+    (no hidden copy is made).
+    """
+    if X.dim() != 2:
+        raise ValueError("operands must be 2-D")
+    r, c = X.shape
+    s0, s1 = X.stride()
+    if s1 == 1 or c <= 1:
+        return "N", max(s0, c, 1)
+    if s0 == 1 or r <= 1:
+        return "T", max(s1, r, 1)
+    raise ValueError(f"operand strides {X.stride()} are neither row- nor column-major")
+
+
+def _stream_ptr(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def gemm(A, B, C=None, *, alpha: float = 1.0, beta: float = 0.0, path="fp32", workspace=None):
+    """C <- alpha * A @ B + beta * C on the GPU, with A (M x K) and B (K x N) float32.
+
+    A and B may be row-major or transposed views; C must be row-major
+    (contiguous rows).  If C is None a new M x N tensor is returned (and beta
+    must be 0).  ``path`` is "fp32", "bf16x3", "bf16" or "fp8".
+    """
+    import torch
+    if A.dtype != torch.float32 or B.dtype != torch.float32:
+        raise TypeError("A and B must be float32")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be on the GPU")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError(f"inner dimensions differ: {tuple(A.shape)} x {tuple(B.shape)}")
+    if C is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs an input C")
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    if C.dtype != torch.float32 or tuple(C.shape) != (M, N) or not C.is_cuda:
+        raise ValueError("C must be a float32 M x N GPU tensor")
+    if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
+        raise ValueError("C must have unit column stride")
+    for X in (A, B):
+        if X.numel() and C.numel() and X.data_ptr() == C.data_ptr():
+            raise ValueError("C must not alias A or B")
+    tA, lda = operand_layout(A)
+    tB, ldb = operand_layout(B)
+    ldc = max(C.stride(0), N, 1)
+    pid = _path_id(path)
+    need = _native.mg_gemm_workspace_size(pid, tA, tB, M, N, K)
+    ws_ptr, ws_bytes = None, 0
+    if need:
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = _native.mg_gemm(pid, tA, tB, M, N, K, float(alpha), A.data_ptr(), lda, B.data_ptr(), ldb,
+                         float(beta), C.data_ptr(), ldc, ws_ptr, ws_bytes, _stream_ptr(A.device))
+    check(st, "mg_gemm")
+    return C

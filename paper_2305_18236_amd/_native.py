@@ -1,0 +1,92 @@
+"""ctypes binding of libmgemm.so: argument marshalling only.
+
+Every function here has the name and argument order of the C entry point
+declared in include/mgemm.h and passes raw device pointers and sizes through.
+No arithmetic of the GEMM happens in Python.  If the library has not been
+built, loading fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgemm.so")
+
+_lib = None
+
+
+class MgemmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)})")
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_18236_amd.build` "
+                          "(the HIP library is required; there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, f32, vp, ch, ci = ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_char, ctypes.c_int
+    L.mg_sgemm.argtypes = [ch, ch, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]
+    L.mg_sgemm.restype = ci
+    L.mg_gemm.argtypes = [ci, ch, ch, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp,
+                          ctypes.c_size_t, vp]
+    L.mg_gemm.restype = ci
+    L.mg_gemm_workspace_size.argtypes = [ci, ch, ch, i64, i64, i64]
+    L.mg_gemm_workspace_size.restype = ctypes.c_size_t
+    L.mg_num_configs.argtypes = [ci]
+    L.mg_num_configs.restype = ci
+    L.mg_config_info.argtypes = [ci, ci, ctypes.POINTER(ci)]
+    L.mg_config_info.restype = ci
+    L.mg_force_config.argtypes = [ci, ci]
+    L.mg_force_config.restype = ci
+    L.mg_status_string.argtypes = [ci]
+    L.mg_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _c(t) -> bytes:
+    return t.encode() if isinstance(t, str) else bytes(t)
+
+
+def status_string(status: int) -> str:
+    return lib().mg_status_string(int(status)).decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        raise MgemmError(status, where)
+
+
+def mg_sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream) -> int:
+    return lib().mg_sgemm(_c(transA), _c(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream)
+
+
+def mg_gemm(path, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+            workspace, workspace_bytes, stream) -> int:
+    return lib().mg_gemm(int(path), _c(transA), _c(transB), M, N, K, alpha, A, lda, B, ldb, beta,
+                         C, ldc, workspace, workspace_bytes, stream)
+
+
+def mg_gemm_workspace_size(path, transA, transB, M, N, K) -> int:
+    return int(lib().mg_gemm_workspace_size(int(path), _c(transA), _c(transB), M, N, K))
+
+
+def mg_num_configs(path) -> int:
+    return int(lib().mg_num_configs(int(path)))
+
+
+def mg_config_info(path, index):
+    out = (ctypes.c_int * 6)()
+    st = lib().mg_config_info(int(path), int(index), out)
+    check(st, "mg_config_info")
+    return dict(zip(("id", "bm", "bn", "bk", "wm", "wn"), list(out)))
+
+
+def mg_force_config(path, config_id) -> int:
+    return int(lib().mg_force_config(int(path), int(config_id)))

@@ -1,0 +1,60 @@
+// Shared device-side helpers of the mgemm kernels (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+#define MG_DEVICE __device__ __forceinline__
+
+namespace mg {
+
+// Arguments of one GEMM, as the kernels see them.  Strides are row strides of
+// the stored matrices in elements; trans flags say whether op(X) = X^T.
+struct GemmArgs {
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+    int tiles_m, tiles_n;
+    int group_m;      // tile rows per raster group (L2 reuse of B panels)
+    int vec_a, vec_b, vec_c;   // 16-byte vector access allowed for A, B, C
+};
+
+// Map a linear workgroup id to an output tile (tm, tn).
+//
+// Hardware hands consecutive workgroup ids to the 8 XCDs round-robin.  We
+// first undo that, so that each XCD owns a contiguous range of logical ids,
+// then walk that range in groups of `group_m` tile rows, column by column,
+// so that workgroups resident on one XCD at the same time share A row panels
+// and B column panels in that XCD's L2.
+MG_DEVICE void tile_of(int pid, int tiles_m, int tiles_n, int group_m, int& tm, int& tn)
+{
+    const int total = tiles_m * tiles_n;
+    constexpr int XCDS = 8;
+    if (total % XCDS == 0) {
+        const int per = total / XCDS;
+        pid = (pid % XCDS) * per + pid / XCDS;
+    }
+    const int in_group = group_m * tiles_n;
+    const int g = pid / in_group;
+    const int first_m = g * group_m;
+    const int rows = min(tiles_m - first_m, group_m);
+    const int local = pid - g * in_group;
+    tm = first_m + local % rows;
+    tn = local / rows;
+}
+
+MG_DEVICE floatx16 mfma_f32_32x32x2(float a, float b, floatx16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+}  // namespace mg

@@ -1,0 +1,22 @@
+// Internal (C++ linkage) interface between the C-ABI host layer and the
+// kernel translation units.  Not part of the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mg {
+
+struct SgemmConfig {
+    int id, bm, bn, bk, wm, wn;
+};
+
+extern const SgemmConfig kSgemmConfigs[];
+extern const int kNumSgemmConfigs;
+
+hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
+hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
+
+}  // namespace mg

@@ -1,0 +1,168 @@
+// C-ABI host layer of mgemm: argument validation, BLAS quick returns,
+// configuration choice (the blocking decision of Section 3.1) and launch on
+// the caller's stream.  Every check here runs on the host before any device
+// call, so invalid arguments never reach a kernel.
+#include <atomic>
+#include <climits>
+
+#include "../../include/mgemm.h"
+#include "kernels.h"
+
+namespace {
+
+bool is_n(char t) { return t == 'N' || t == 'n'; }
+bool is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+
+std::atomic<int> g_forced[4] = {{-1}, {-1}, {-1}, {-1}};
+
+int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP - int(e); }
+
+// rows * ld must stay addressable; both are non-negative here.
+bool fits(int64_t rows, int64_t ld) { return rows == 0 || ld <= INT64_MAX / 4 / rows; }
+
+// BLAS-style validation of the mg_sgemm argument list.
+int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, const float* A,
+             int64_t lda, const float* B, int64_t ldb, const float* C, int64_t ldc)
+{
+    if (!is_n(transA) && !is_t(transA)) return -1;
+    if (!is_n(transB) && !is_t(transB)) return -2;
+    if (M < 0) return -3;
+    if (N < 0) return -4;
+    if (K < 0) return -5;
+    const bool ta = is_t(transA), tb = is_t(transB);
+    const int64_t a_rows = ta ? K : M, a_cols = ta ? M : K;
+    const int64_t b_rows = tb ? N : K, b_cols = tb ? K : N;
+    if (A == nullptr && M > 0 && K > 0) return -7;
+    if (lda < (a_cols > 1 ? a_cols : 1) || !fits(a_rows, lda)) return -8;
+    if (B == nullptr && K > 0 && N > 0) return -9;
+    if (ldb < (b_cols > 1 ? b_cols : 1) || !fits(b_rows, ldb)) return -10;
+    if (C == nullptr && M > 0 && N > 0) return -12;
+    if (ldc < (N > 1 ? N : 1) || !fits(M, ldc)) return -13;
+    if (M > INT_MAX || N > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    return MG_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int64_t tiles(int64_t M, int64_t N, int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); }
+
+// Automatic FP32 configuration: the largest workgroup tile that still gives
+// every compute unit at least one tile; small problems fall back to smaller
+// tiles so that more of the 256 CUs take part.
+int choose_sgemm_config(int64_t M, int64_t N, int64_t K)
+{
+    (void)K;
+    if (tiles(M, N, 256, 256) >= 256) return 1;
+    if (tiles(M, N, 256, 128) >= 256) return 2;
+    if (tiles(M, N, 128, 128) >= 128) return 0;
+    return 3;
+}
+
+int run_sgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+              int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc,
+              hipStream_t stream)
+{
+    int cfg = g_forced[MG_PATH_FP32].load();
+    if (cfg < 0) cfg = choose_sgemm_config(M, N, K);
+    const mg::SgemmConfig& c = mg::kSgemmConfigs[cfg];
+    if (tiles(M, N, c.bm, c.bn) > INT_MAX) return MG_ERR_TOO_LARGE;
+    mg::GemmArgs g{};
+    g.A = A; g.B = B; g.C = C;
+    g.M = M; g.N = N; g.K = K;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.group_m = 4;
+    g.vec_a = aligned16(A) && lda % 4 == 0;
+    g.vec_b = aligned16(B) && ldb % 4 == 0;
+    g.vec_c = aligned16(C) && ldc % 4 == 0;
+    return hip_status(mg::launch_sgemm(cfg, ta, tb, g, stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+            const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+            int64_t ldc, void* workspace, size_t workspace_bytes, void* stream)
+{
+    (void)workspace;
+    (void)workspace_bytes;
+    int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
+    if (st != MG_OK) return st;
+    if (path != MG_PATH_FP32) return MG_ERR_UNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (M == 0 || N == 0) return MG_OK;
+    if (K == 0 || alpha == 0.f) {
+        if (beta == 1.f) return MG_OK;
+        return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
+    }
+    return run_sgemm(is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+             const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+             int64_t ldc, void* stream)
+{
+    return mg_gemm(MG_PATH_FP32, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                   nullptr, 0, stream);
+}
+
+size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
+{
+    (void)transA; (void)transB; (void)M; (void)N; (void)K;
+    (void)path;
+    return 0;
+}
+
+int mg_num_configs(int path)
+{
+    if (path == MG_PATH_FP32) return mg::kNumSgemmConfigs;
+    return 0;
+}
+
+int mg_config_info(int path, int index, int* out6)
+{
+    if (out6 == nullptr) return MG_ERR_UNSUPPORTED;
+    if (path == MG_PATH_FP32 && index >= 0 && index < mg::kNumSgemmConfigs) {
+        const mg::SgemmConfig& c = mg::kSgemmConfigs[index];
+        out6[0] = c.id; out6[1] = c.bm; out6[2] = c.bn; out6[3] = c.bk; out6[4] = c.wm; out6[5] = c.wn;
+        return MG_OK;
+    }
+    return MG_ERR_UNSUPPORTED;
+}
+
+int mg_force_config(int path, int config_id)
+{
+    if (path < 0 || path > 3) return MG_ERR_UNSUPPORTED;
+    if (config_id < -1 || config_id >= mg_num_configs(path)) return MG_ERR_UNSUPPORTED;
+    g_forced[path].store(config_id);
+    return MG_OK;
+}
+
+const char* mg_status_string(int status)
+{
+    switch (status) {
+    case MG_OK: return "success";
+    case -1: return "invalid argument 1 (transA)";
+    case -2: return "invalid argument 2 (transB)";
+    case -3: return "invalid argument 3 (M < 0)";
+    case -4: return "invalid argument 4 (N < 0)";
+    case -5: return "invalid argument 5 (K < 0)";
+    case -7: return "invalid argument 7 (A is NULL)";
+    case -8: return "invalid argument 8 (lda too small or too large)";
+    case -9: return "invalid argument 9 (B is NULL)";
+    case -10: return "invalid argument 10 (ldb too small or too large)";
+    case -12: return "invalid argument 12 (C is NULL)";
+    case -13: return "invalid argument 13 (ldc too small or too large)";
+    case MG_ERR_WORKSPACE: return "workspace missing or too small";
+    case MG_ERR_UNSUPPORTED: return "unsupported path or configuration";
+    case MG_ERR_TOO_LARGE: return "dimension too large for the kernels";
+    case MG_ERR_BAD_TABLE: return "tuning table unreadable or malformed";
+    default: break;
+    }
+    if (status <= MG_ERR_HIP) return hipGetErrorString(hipError_t(MG_ERR_HIP - status));
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""Shared helpers of the GPU parity tests: stage seeded host operands on the
+device in a given stored layout, call the library through its C ABI, and score
+the result against the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import seeded_inputs as si
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp8": 6e-2}
+PATH_ID = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+
+
+def device_buffer(host_1d: np.ndarray, torch_device):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(host_1d, dtype=np.float32))
+    return t.to(torch_device)
+
+
+class Problem:
+    """One GEMM instance: logical operands, their stored layouts and the oracle result."""
+
+    def __init__(self, M, N, K, tA="N", tB="N", alpha=1.0, beta=0.0, seed=0, dist="uniform",
+                 lda=None, ldb=None, ldc=None, c0_nan=False):
+        self.M, self.N, self.K = M, N, K
+        self.tA, self.tB = tA, tB
+        self.alpha, self.beta = alpha, beta
+        gen = {"uniform": si.uniform, "integers": si.integers, "log": si.log_uniform_signed}[dist]
+        self.opA = gen((M, K), seed * 10 + 0)
+        self.opB = gen((K, N), seed * 10 + 1)
+        if c0_nan:
+            self.C0 = np.full((M, N), np.nan, np.float32)
+        else:
+            self.C0 = gen((M, N), seed * 10 + 2)
+        self.A, self.lda = si.store(self.opA, tA, lda)
+        self.B, self.ldb = si.store(self.opB, tB, ldb)
+        self.ldc = N if ldc is None else ldc
+        Cbuf = np.full((max(M, 1), max(self.ldc, 1)), -7.0, np.float32)
+        Cbuf[:M, :N] = self.C0
+        self.Cbuf = Cbuf.reshape(-1)
+
+    def oracle(self, threads=None):
+        return oracle.gemm(self.tA, self.tB, self.M, self.N, self.K, self.alpha, self.A, self.lda,
+                           self.B, self.ldb, self.beta, self.C0, self.N, threads=threads)
+
+    def oracle_entries(self, I, J, threads=None):
+        return oracle.gemm_entries(self.tA, self.tB, self.K, self.alpha, self.A, self.lda, self.B,
+                                   self.ldb, self.beta, self.C0, self.N, I, J, threads=threads)
+
+    def to_device(self, dev):
+        self.dA = device_buffer(self.A if self.A.size else np.zeros(1, np.float32), dev)
+        self.dB = device_buffer(self.B if self.B.size else np.zeros(1, np.float32), dev)
+        self.dC = device_buffer(self.Cbuf, dev)
+        return self
+
+    def reset_c(self):
+        import torch
+        self.dC.copy_(torch.from_numpy(self.Cbuf))
+
+    def run(self, path="fp32", workspace=None, stream=None):
+        """Call mg_gemm through the C ABI; returns the status code."""
+        import torch
+        from paper_2305_18236_amd import _native
+        pid = PATH_ID[path]
+        need = _native.mg_gemm_workspace_size(pid, self.tA, self.tB, self.M, self.N, self.K)
+        ws_ptr, ws_bytes = None, 0
+        if need:
+            if workspace is None or workspace.numel() < need:
+                workspace = torch.empty(need, dtype=torch.uint8, device=self.dA.device)
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dA.device).cuda_stream
+        return _native.mg_gemm(pid, self.tA, self.tB, self.M, self.N, self.K, self.alpha,
+                               self.dA.data_ptr(), self.lda, self.dB.data_ptr(), self.ldb, self.beta,
+                               self.dC.data_ptr(), self.ldc, ws_ptr, ws_bytes, stream)
+
+    def result(self) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize()
+        full = self.dC.cpu().numpy().reshape(max(self.M, 1), max(self.ldc, 1))
+        return full[:self.M, :self.N].astype(np.float64)
+
+    def padding_untouched(self) -> bool:
+        import torch
+        torch.cuda.synchronize()
+        full = self.dC.cpu().numpy().reshape(max(self.M, 1), max(self.ldc, 1))
+        return bool(np.all(full[:self.M, self.N:] == -7.0))

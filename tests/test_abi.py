@@ -1,0 +1,103 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+public header declares, and rejects invalid arguments on the host (before any
+device call), with the documented BLAS-style codes."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgemm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2305_18236_amd import _native
+    _native.lib()
+    return _native
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mg_sgemm", "mg_gemm", "mg_gemm_workspace_size", "mg_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(native):
+    L = ctypes.CDLL(native.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+FAKE = 0x1000   # never dereferenced: validation fails before any device call
+
+
+def _call(native, **kw):
+    a = dict(transA="N", transB="N", M=4, N=5, K=6, alpha=1.0, A=FAKE, lda=6, B=FAKE, ldb=5,
+             beta=0.0, C=FAKE, ldc=5, stream=None)
+    a.update(kw)
+    return native.mg_sgemm(a["transA"], a["transB"], a["M"], a["N"], a["K"], a["alpha"], a["A"],
+                           a["lda"], a["B"], a["ldb"], a["beta"], a["C"], a["ldc"], a["stream"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(transA="X"), -1), (dict(transB="Q"), -2), (dict(M=-1), -3), (dict(N=-2), -4),
+    (dict(K=-3), -5), (dict(A=None), -7), (dict(lda=5), -8), (dict(B=None), -9),
+    (dict(ldb=4), -10), (dict(C=None), -12), (dict(ldc=4), -13),
+    # transposed storage changes the minimum leading dimensions
+    (dict(transA="T", lda=3), -8), (dict(transB="t", ldb=5), -10),
+    # overflow of rows * ld
+    (dict(lda=2 ** 62), -8),
+    # first invalid argument wins (BLAS order)
+    (dict(transA="X", M=-1), -1), (dict(M=-1, lda=0), -3),
+])
+def test_invalid_arguments_rejected_on_host(native, kw, code):
+    assert _call(native, **kw) == code
+
+
+def test_null_pointer_allowed_for_empty_extent(native):
+    # M == 0: A and C have no elements; quick return without touching anything
+    assert _call(native, M=0, A=None, C=None) == 0
+    # N == 0: B and C empty
+    assert _call(native, N=0, B=None, C=None, ldb=1, ldc=1) == 0
+
+
+def test_status_strings(native):
+    for code in (0, -1, -2, -3, -4, -5, -7, -8, -9, -10, -12, -13, -100, -101, -102, -103):
+        s = native.status_string(code)
+        assert s and s != "unknown status"
+    assert native.status_string(12345) == "unknown status"
+
+
+def test_config_registry(native):
+    n = native.mg_num_configs(0)
+    assert n >= 1
+    for i in range(n):
+        c = native.mg_config_info(0, i)
+        assert c["id"] == i and c["bm"] % c["wm"] == 0 and c["bn"] % c["wn"] == 0
+        assert c["bk"] % 2 == 0
+        # LDS budget of a double-buffered FP32 panel pair (160 KiB per CU on gfx950)
+        assert 2 * (c["bm"] + c["bn"]) * c["bk"] * 4 <= 160 * 1024
+    assert native.mg_force_config(0, n) == -101
+    assert native.mg_force_config(9, 0) == -101
+    assert native.mg_force_config(0, -1) == 0
+
+
+def test_operand_layout_from_strides():
+    from paper_2305_18236_amd import operand_layout
+    X = torch.empty(5, 7)
+    assert operand_layout(X) == ("N", 7)
+    assert operand_layout(X.t()) == ("T", 7)
+    big = torch.empty(5, 12)
+    assert operand_layout(big[:, :7]) == ("N", 12)
+    assert operand_layout(big[:, :7].t()) == ("T", 12)
+    with pytest.raises(ValueError):
+        operand_layout(torch.empty(4, 6)[:, ::2])

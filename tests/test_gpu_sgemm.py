@@ -1,0 +1,142 @@
+"""GPU parity of the FP32-MFMA path against the FP64 oracle, through the C ABI.
+
+Bar: normalised error max|C - C_ref| / (|alpha||A||B| + |beta||C0|) <= 1e-5,
+and bit-exact results where the inputs make the exact result representable
+(integer-valued operands).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from helpers import Problem, TOL
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = list(itertools.product("NT", "NT"))
+
+
+def _native():
+    from paper_2305_18236_amd import _native
+    return _native
+
+
+def _check(p, dev, path="fp32", tol=None, cfg=None):
+    nat = _native()
+    if cfg is not None:
+        assert nat.mg_force_config(0, cfg) == 0
+    try:
+        p.to_device(dev)
+        st = p.run(path)
+        assert st == 0, nat.status_string(st)
+        C = p.result()
+    finally:
+        nat.mg_force_config(0, -1)
+    Cref, D = p.oracle()
+    err = oracle.normalized_error(C, Cref, D)
+    assert err <= (TOL[path] if tol is None else tol), (p.M, p.N, p.K, p.tA, p.tB, err)
+    assert p.padding_untouched()
+    return C, Cref, err
+
+
+def test_config1_256_cube_nn(gpu):
+    """M = N = K = 256, NN, alpha = 1, beta = 0, U[-1, 1]."""
+    p = Problem(256, 256, 256, "N", "N", 1.0, 0.0, seed=1000)
+    _check(p, gpu)
+
+
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+@pytest.mark.parametrize("M,N,K", [(300, 517, 129), (1, 1, 1), (7, 9, 8), (33, 65, 31),
+                                   (129, 257, 64), (64, 64, 1000), (5, 300, 3)])
+def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
+    p = Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + 7 * N + 13 * K)
+    _check(p, gpu)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+def test_every_config_every_layout(gpu, cfg, tA, tB):
+    """Each tile configuration over several tiles and a ragged tail."""
+    p = Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg * 4 + ord(tA) + ord(tB))
+    _check(p, gpu, cfg=cfg)
+
+
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+def test_integer_inputs_bit_exact(gpu, tA, tB):
+    """Integers in [-8, 8]: partial sums stay below 2^24, so the exact result
+    is representable and any summation order gives it."""
+    p = Problem(200, 300, 250, tA, tB, 1.5, 0.5, seed=77, dist="integers")
+    C, Cref, _ = _check(p, gpu)
+    assert np.array_equal(C, Cref)
+
+
+def test_padded_leading_dimensions_and_misaligned(gpu):
+    """lda/ldb/ldc above the minimum and not multiples of 4 (scalar paths)."""
+    p = Problem(70, 45, 33, "T", "N", 1.0, 0.5, seed=5, lda=71, ldb=47, ldc=49)
+    _check(p, gpu)
+    p = Problem(70, 45, 33, "N", "T", 1.0, 0.5, seed=6, lda=36, ldb=40, ldc=48)
+    _check(p, gpu)
+
+
+def test_beta_zero_never_reads_c(gpu):
+    p = Problem(100, 130, 40, "N", "N", 1.0, 0.0, seed=8, c0_nan=True)
+    p.to_device(gpu)
+    assert p.run() == 0
+    C = p.result()
+    assert not np.isnan(C).any()
+    Cref, D = oracle.gemm("N", "N", 100, 130, 40, 1.0, p.A, p.lda, p.B, p.ldb)
+    assert oracle.normalized_error(C, Cref, D) <= TOL["fp32"]
+
+
+def test_alpha_zero_and_k_zero_scale_c(gpu):
+    p = Problem(50, 60, 20, "N", "N", 0.0, 0.5, seed=9)
+    p.opA[:] = np.nan   # alpha == 0: A must not be read
+    p.A[:] = np.nan
+    p.to_device(gpu)
+    assert p.run() == 0
+    assert np.array_equal(p.result(), 0.5 * p.C0.astype(np.float64))
+    # beta == 0 with NaN C: zeros
+    q = Problem(50, 60, 20, "N", "N", 0.0, 0.0, seed=10, c0_nan=True)
+    q.to_device(gpu)
+    assert q.run() == 0
+    assert np.array_equal(q.result(), np.zeros((50, 60)))
+    # beta == 1: untouched
+    r = Problem(50, 60, 20, "N", "N", 0.0, 1.0, seed=11)
+    r.to_device(gpu)
+    assert r.run() == 0
+    assert np.array_equal(r.result(), r.C0.astype(np.float64))
+
+
+def test_m_or_n_zero_touches_nothing(gpu):
+    p = Problem(0, 5, 7, seed=12)
+    p.to_device(gpu)
+    assert p.run() == 0
+
+
+def test_deterministic_bitwise(gpu):
+    """No atomics in the reduction: repeated runs give identical bits; a
+    missing barrier or an LDS race would show up here."""
+    p = Problem(1000, 900, 700, "N", "N", 1.5, 0.5, seed=13).to_device(gpu)
+    outs = []
+    for _ in range(3):
+        p.reset_c()
+        assert p.run() == 0
+        outs.append(p.result())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+def test_full_size_8192_sampled(gpu, tA, tB):
+    """The benchmark's launch: 8192^3, alpha 1.5, beta 0.5, in every layout;
+    4096 sampled outputs (corners included) against the oracle."""
+    p = Problem(8192, 8192, 8192, tA, tB, 1.5, 0.5, seed=1001).to_device(gpu)
+    assert p.run() == 0
+    C = p.result()
+    I, J = si.sample_indices(8192, 8192, 4096, 99)
+    cref, d = p.oracle_entries(I, J)
+    err = oracle.normalized_error(C[I, J], cref, d)
+    assert err <= TOL["fp32"], err
+    assert np.isfinite(C).all()
