@@ -1,0 +1,231 @@
+"""Benchmark of the layered GEMM on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: FP32 SGEMM, M = N = K = 8192, row-major NN, alpha = 1.5, beta = 0.5,
+A, B, C entries i.i.d. uniform[-1, 1] (seeded, synthetic).  One step is one
+full GEMM C <- alpha*A*B + beta*C on the FP32-MFMA path with all operands
+resident in HBM.  The same problem is also timed on the bf16x3 split path
+(FP32 accuracy from BF16 matrix cores) for the speedup figure.
+
+Prints one JSON line.  `value` is FP32 TFLOP/s = 2*M*N*K / (mean step time).
+`roofline` reports the dominant kernel (the FP32 GEMM kernel) against the FP32
+MFMA peak, from per-launch HIP events on the launch stream.  `cpu_baseline`
+times the FP64 oracle on a bounded sample of the same GEMM (a block of output
+rows) on the host cores, and the same sample gives the sampled normalised error
+of each GPU path.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "GEMM TFLOP/s & % MFMA peak at 8192³; bf16x3 vs FP32 speedup at ≤1e-5 rel err"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+M = N = K = 8192
+ALPHA, BETA = 1.5, 0.5
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sgemm_f32_8192_nn_traffic.md")
+KERNEL_SOURCES = ["paper_2305_18236_amd/csrc/gemm_f32.hip", "paper_2305_18236_amd/csrc/common.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    vals = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_path(path, A, B, C, steps, warmup, torch, native):
+    """Run `warmup` + `steps` GEMMs on the current stream; per-launch HIP events."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    need = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+
+    def launch():
+        st = native.mg_gemm(pid, "N", "N", M, N, K, ALPHA, A.data_ptr(), K, B.data_ptr(), N, BETA,
+                            C.data_ptr(), N, ws.data_ptr(), need, sp)
+        native.check(st, "mg_gemm")
+
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        launch()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    total_ms = ev[0].elapsed_time(ev[steps])
+    return {"ms_per_step": total_ms / steps, "kernel_ms_mean": float(np.mean(per)),
+            "kernel_ms_median": float(np.median(per)), "wall_s": wall}
+
+
+def single_result(path, A, B, C0_dev, torch, native):
+    """One GEMM from the original C0 (for the error check)."""
+    C = C0_dev.clone()
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    need = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    st = native.mg_gemm(pid, "N", "N", M, N, K, ALPHA, A.data_ptr(), K, B.data_ptr(), N, BETA,
+                        C.data_ptr(), N, ws.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+    native.check(st, "mg_gemm")
+    torch.cuda.synchronize()
+    return C
+
+
+def cpu_baseline(A_h, B_h, C0_h, gpu_rows, target_s=12.0):
+    """Time the FP64 oracle on a block of output rows of the same GEMM, and
+    score the GPU results on those rows."""
+    import oracle
+    threads = oracle.max_threads()
+    # calibrate on one row, then size the block to about target_s seconds
+    t0 = time.perf_counter()
+    oracle.gemm("N", "N", 1, N, K, ALPHA, A_h[:K], K, B_h, N, BETA, C0_h[:N], N, threads=threads)
+    t1 = time.perf_counter() - t0
+    rows = int(max(threads, min(512, target_s / max(t1, 1e-6) * threads / 2)))
+    rows = max(threads, (rows // threads) * threads)
+    t0 = time.perf_counter()
+    Cref, D = oracle.gemm("N", "N", rows, N, K, ALPHA, A_h[: rows * K], K, B_h, N, BETA,
+                          C0_h[: rows * N], N, threads=threads)
+    dt = time.perf_counter() - t0
+    errs = {p: oracle.normalized_error(g[:rows].astype(np.float64), Cref, D) for p, g in gpu_rows.items()}
+    return {"value": 2.0 * rows * N * K / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {rows} of {M} output rows of the same 8192^3 GEMM "
+                      f"({rows * N} outputs, full K), FP64 triple loop, {dt:.1f} s"}, errs, rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build targets one GPU; runs on more than one GPU are not supported "
+              "(a GEMM shards as independent output tiles; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import seeded_inputs as si
+    from paper_2305_18236_amd import _native
+    native = _native
+    native.lib()
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
+
+    A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
+    B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
+    C0_h = si.uniform((M, N), si.seed_for(2, "C")).reshape(-1)
+    A = torch.from_numpy(A_h).to(dev)
+    B = torch.from_numpy(B_h).to(dev)
+    C0 = torch.from_numpy(C0_h).to(dev)
+
+    flops = 2.0 * M * N * K
+    results = {}
+    paths = ["fp32"] + [p for p in ("bf16x3",) if _path_supported(native, p)]
+    for path in paths:
+        C = C0.clone()
+        r = time_path(path, A, B, C, args.steps, args.warmup, torch, native)
+        r["tflops"] = flops / (r["ms_per_step"] * 1e-3) / 1e12
+        r["kernel_tflops"] = flops / (r["kernel_ms_mean"] * 1e-3) / 1e12
+        results[path] = r
+        del C
+
+    f32 = results["fp32"]
+    peak = PEAK_TFLOPS["fp32"]
+    achieved = f32["kernel_tflops"]
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": round(f32["tflops"], 2),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sgemm_fp32_8192x8192x8192_nn", "M": M, "N": N, "K": K,
+                   "layout": "NN", "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]",
+                   "path": "fp32"},
+        "pct_fp32_mfma_peak": round(100.0 * f32["tflops"] / peak, 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "kernel": "sgemm_mfma_kernel<256,256,16,128,128,NN>",
+                     "kernel_ms_mean": round(f32["kernel_ms_mean"], 4),
+                     "algorithmic_flops_per_launch": flops},
+    }
+    if "bf16x3" in results:
+        b = results["bf16x3"]
+        out["bf16x3"] = {"tflops": round(b["tflops"], 2), "ms_per_step": round(b["ms_per_step"], 4),
+                         "speedup_vs_fp32": round(b["tflops"] / f32["tflops"], 3),
+                         "pct_bf16_mfma_peak_issued": round(100.0 * 3 * b["tflops"] / PEAK_TFLOPS["bf16"], 2)}
+
+    if not args.no_cpu_baseline:
+        rows_needed = 512
+        gpu_rows = {}
+        for path in results:
+            Cp = single_result(path, A, B, C0, torch, native)
+            gpu_rows[path] = Cp[: rows_needed * N].cpu().numpy().reshape(rows_needed, N)
+        cb, errs, rows = cpu_baseline(A_h, B_h, C0_h, gpu_rows)
+        out["cpu_baseline"] = cb
+        out["sampled_error_vs_fp64_oracle"] = {p: float(f"{e:.3e}") for p, e in errs.items()}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def _path_supported(native, path) -> bool:
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    return native.mg_num_configs(pid) > 0
+
+
+if __name__ == "__main__":
+    main()
