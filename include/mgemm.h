@@ -110,6 +110,16 @@ int mg_config_info(int path, int index, int *out6);
  */
 int mg_force_config(int path, int config_id);
 
+/*
+ * The pack-stage conversion of the BF16 paths on its own (Table 1's bf16
+ * operand type, round to nearest even): hi[t] = bf16(x[t]) and, when lo is
+ * not NULL, lo[t] = bf16(x[t] - hi[t]), as raw bf16 bit patterns.  x, hi, lo
+ * are device arrays of n elements.  Runs the same device conversion the
+ * bf16x3 and BF16 GEMMs use, so its output can be checked bit for bit.
+ * Errors: -1 x NULL, -2 n < 0, -3 hi NULL (n > 0).
+ */
+int mg_bf16_split(const float *x, int64_t n, uint16_t *hi, uint16_t *lo, void *stream);
+
 /* Human-readable description of a status code (static storage). */
 const char *mg_status_string(int status);
 

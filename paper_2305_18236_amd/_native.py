@@ -44,6 +44,8 @@ def lib():
     L.mg_config_info.restype = ci
     L.mg_force_config.argtypes = [ci, ci]
     L.mg_force_config.restype = ci
+    L.mg_bf16_split.argtypes = [vp, i64, vp, vp, vp]
+    L.mg_bf16_split.restype = ci
     L.mg_status_string.argtypes = [ci]
     L.mg_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -75,6 +77,10 @@ def mg_gemm(path, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
 
 def mg_gemm_workspace_size(path, transA, transB, M, N, K) -> int:
     return int(lib().mg_gemm_workspace_size(int(path), _c(transA), _c(transB), M, N, K))
+
+
+def mg_bf16_split(x, n, hi, lo, stream) -> int:
+    return lib().mg_bf16_split(x, n, hi, lo, stream)
 
 
 def mg_num_configs(path) -> int:

@@ -17,6 +17,13 @@ extern const SgemmConfig kSgemmConfigs[];
 extern const int kNumSgemmConfigs;
 
 hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
+extern const SgemmConfig kBf16Configs[];
+extern const int kNumBf16Configs;
+
+// terms == 1: plain BF16; terms == 3: bf16x3 split.
+hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
+hipError_t launch_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
+
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
 }  // namespace mg

@@ -46,25 +46,47 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 int64_t tiles(int64_t M, int64_t N, int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); }
 
-// Automatic FP32 configuration: the largest workgroup tile that still gives
-// every compute unit at least one tile; small problems fall back to smaller
-// tiles so that more of the 256 CUs take part.
-int choose_sgemm_config(int64_t M, int64_t N, int64_t K)
+struct ConfigTable {
+    const mg::SgemmConfig* cfgs;
+    int n;
+};
+
+ConfigTable table_of(int path)
 {
-    (void)K;
-    if (tiles(M, N, 256, 256) >= 256) return 1;
-    if (tiles(M, N, 256, 128) >= 256) return 2;
-    if (tiles(M, N, 128, 128) >= 128) return 0;
-    return 3;
+    switch (path) {
+    case MG_PATH_FP32: return {mg::kSgemmConfigs, mg::kNumSgemmConfigs};
+    case MG_PATH_BF16X3:
+    case MG_PATH_BF16: return {mg::kBf16Configs, mg::kNumBf16Configs};
+    default: return {nullptr, 0};
+    }
 }
 
-int run_sgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
-              int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc,
-              hipStream_t stream)
+// Automatic configuration: the largest workgroup tile that still gives every
+// compute unit at least one tile; smaller problems fall back to smaller tiles
+// so that more of the 256 CUs take part.
+int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
-    int cfg = g_forced[MG_PATH_FP32].load();
-    if (cfg < 0) cfg = choose_sgemm_config(M, N, K);
-    const mg::SgemmConfig& c = mg::kSgemmConfigs[cfg];
+    (void)K;
+    if (path == MG_PATH_FP32) {
+        if (tiles(M, N, 256, 256) >= 256) return 1;
+        if (tiles(M, N, 256, 128) >= 256) return 2;
+        if (tiles(M, N, 128, 128) >= 128) return 0;
+        return 3;
+    }
+    if (tiles(M, N, 256, 256) >= 256) return 1;
+    if (tiles(M, N, 256, 128) >= 256) return 3;
+    if (tiles(M, N, 128, 128) >= 128) return 2;
+    return 4;
+}
+
+int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
+             const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+             int64_t ldc, hipStream_t stream)
+{
+    int cfg = g_forced[path].load();
+    if (cfg < 0) cfg = choose_config(path, M, N, K);
+    const ConfigTable t = table_of(path);
+    const mg::SgemmConfig& c = t.cfgs[cfg];
     if (tiles(M, N, c.bm, c.bn) > INT_MAX) return MG_ERR_TOO_LARGE;
     mg::GemmArgs g{};
     g.A = A; g.B = B; g.C = C;
@@ -75,7 +97,12 @@ int run_sgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, co
     g.vec_a = aligned16(A) && lda % 4 == 0;
     g.vec_b = aligned16(B) && ldb % 4 == 0;
     g.vec_c = aligned16(C) && ldc % 4 == 0;
-    return hip_status(mg::launch_sgemm(cfg, ta, tb, g, stream));
+    switch (path) {
+    case MG_PATH_FP32: return hip_status(mg::launch_sgemm(cfg, ta, tb, g, stream));
+    case MG_PATH_BF16X3: return hip_status(mg::launch_gemm_bf16(3, cfg, ta, tb, g, stream));
+    case MG_PATH_BF16: return hip_status(mg::launch_gemm_bf16(1, cfg, ta, tb, g, stream));
+    default: return MG_ERR_UNSUPPORTED;
+    }
 }
 
 }  // namespace
@@ -90,14 +117,14 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
     (void)workspace_bytes;
     int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
     if (st != MG_OK) return st;
-    if (path != MG_PATH_FP32) return MG_ERR_UNSUPPORTED;
+    if (table_of(path).n == 0) return MG_ERR_UNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (M == 0 || N == 0) return MG_OK;
     if (K == 0 || alpha == 0.f) {
         if (beta == 1.f) return MG_OK;
         return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
     }
-    return run_sgemm(is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
 int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
@@ -117,15 +144,15 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int
 
 int mg_num_configs(int path)
 {
-    if (path == MG_PATH_FP32) return mg::kNumSgemmConfigs;
-    return 0;
+    return table_of(path).n;
 }
 
 int mg_config_info(int path, int index, int* out6)
 {
     if (out6 == nullptr) return MG_ERR_UNSUPPORTED;
-    if (path == MG_PATH_FP32 && index >= 0 && index < mg::kNumSgemmConfigs) {
-        const mg::SgemmConfig& c = mg::kSgemmConfigs[index];
+    const ConfigTable t = table_of(path);
+    if (index >= 0 && index < t.n) {
+        const mg::SgemmConfig& c = t.cfgs[index];
         out6[0] = c.id; out6[1] = c.bm; out6[2] = c.bn; out6[3] = c.bk; out6[4] = c.wm; out6[5] = c.wn;
         return MG_OK;
     }
@@ -138,6 +165,15 @@ int mg_force_config(int path, int config_id)
     if (config_id < -1 || config_id >= mg_num_configs(path)) return MG_ERR_UNSUPPORTED;
     g_forced[path].store(config_id);
     return MG_OK;
+}
+
+int mg_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* stream)
+{
+    if (n < 0) return -2;
+    if (n == 0) return MG_OK;
+    if (x == nullptr) return -1;
+    if (hi == nullptr) return -3;
+    return hip_status(mg::launch_bf16_split(x, n, hi, lo, reinterpret_cast<hipStream_t>(stream)));
 }
 
 const char* mg_status_string(int status)

@@ -9,6 +9,20 @@ import oracle
 import seeded_inputs as si
 
 TOL = {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp8": 6e-2}
+
+# bf16x3 leaves a per-product error of at most about 3 * 2^-16 |a||b| (the
+# dropped lo*lo term and the two split residuals, each <= 2^-16).  The 1e-5
+# bar is statistical: it needs enough sign-random terms to average out, so
+# below K = 32 the worst-case bound applies instead.
+BF16X3_WORST = 5e-5
+
+
+def tolerance(path: str, K: int) -> float:
+    if path == "bf16x3" and K < 32:
+        return BF16X3_WORST
+    return TOL[path]
+
+
 PATH_ID = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
 
 
