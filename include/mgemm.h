@@ -120,6 +120,44 @@ int mg_force_config(int path, int config_id);
  */
 int mg_bf16_split(const float *x, int64_t n, uint16_t *hi, uint16_t *lo, void *stream);
 
+/*
+ * FP8 path in two stages, for callers that quantise once and multiply many
+ * times, and for timing the GEMM alone (mg_gemm on MG_PATH_FP8_T128 runs both
+ * stages on its workspace).
+ *
+ * Packed operand format (the pack step of Algorithm 1, Section 3.1, into a
+ * buffer in device memory, in the micro-kernel's access order): for a logical
+ * R x K matrix X, Rp = R rounded up to a multiple of 256 and Kp = K rounded up
+ * to a multiple of 128;
+ *   q      : Rp x Kp bytes, row-major, q[r][k] = E4M3(X[r][k] / s(tile)) (OCP
+ *            E4M3, round to nearest even; zero outside R x K);
+ *   scales : (Rp/128) x (Kp/128) bytes, row-major, the E8M0 code (e + 127) of
+ *            the tile scale s = 2^e, the smallest power of two with
+ *            amax(tile) <= 448 * s (e = 0 for an all-zero tile).
+ * Tiles are 128 x 128 and aligned to (0, 0).  Scales below 2^-127 (tile
+ * maxima under about 2.6e-36) are clamped to 2^-127.
+ *
+ * mg_fp8_packed_size: bytes of q and of scales for an R x K operand.
+ *   Errors -1 R < 0, -2 K < 0.
+ * mg_fp8_pack: pack op(X), R x K, where trans 'N' means X is stored R x K and
+ *   'T' means K x R (row stride ldx).  Pack A with (transA, M, K) and B as
+ *   op(B)^T with (transB == 'N' ? 'T' : 'N', N, K).  q (16-byte aligned) and
+ *   scales are device buffers of at least the sizes above.
+ *   Errors -1 trans, -2 R < 0, -3 K < 0, -4 X NULL, -5 ldx, -6 q NULL,
+ *   -7 scales NULL.
+ * mg_gemm_fp8_packed: C <- alpha * dequant(qA) * dequant(qB)^T + beta * C for
+ *   packed op(A) (M x K) and op(B)^T (N x K), FP32 accumulation.
+ *   Errors -1 M, -2 N, -3 K, -5 qA/sA NULL or qA misaligned, -7 qB/sB NULL or
+ *   misaligned, -10 C NULL, -11 ldc.
+ */
+int mg_fp8_packed_size(int64_t R, int64_t K, size_t *q_bytes, size_t *scale_bytes);
+int mg_fp8_pack(char trans, int64_t R, int64_t K, const float *X, int64_t ldx,
+                uint8_t *q, uint8_t *scales, void *stream);
+int mg_gemm_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha,
+                       const uint8_t *qA, const uint8_t *sA,
+                       const uint8_t *qB, const uint8_t *sB,
+                       float beta, float *C, int64_t ldc, void *stream);
+
 /* Human-readable description of a status code (static storage). */
 const char *mg_status_string(int status);
 

@@ -46,6 +46,13 @@ def lib():
     L.mg_force_config.restype = ci
     L.mg_bf16_split.argtypes = [vp, i64, vp, vp, vp]
     L.mg_bf16_split.restype = ci
+    sz = ctypes.c_size_t
+    L.mg_fp8_packed_size.argtypes = [i64, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.mg_fp8_packed_size.restype = ci
+    L.mg_fp8_pack.argtypes = [ch, i64, i64, vp, i64, vp, vp, vp]
+    L.mg_fp8_pack.restype = ci
+    L.mg_gemm_fp8_packed.argtypes = [i64, i64, i64, f32, vp, vp, vp, vp, f32, vp, i64, vp]
+    L.mg_gemm_fp8_packed.restype = ci
     L.mg_status_string.argtypes = [ci]
     L.mg_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -81,6 +88,21 @@ def mg_gemm_workspace_size(path, transA, transB, M, N, K) -> int:
 
 def mg_bf16_split(x, n, hi, lo, stream) -> int:
     return lib().mg_bf16_split(x, n, hi, lo, stream)
+
+
+def mg_fp8_packed_size(R, K):
+    q = ctypes.c_size_t()
+    s = ctypes.c_size_t()
+    check(lib().mg_fp8_packed_size(R, K, ctypes.byref(q), ctypes.byref(s)), "mg_fp8_packed_size")
+    return int(q.value), int(s.value)
+
+
+def mg_fp8_pack(trans, R, K, X, ldx, q, scales, stream) -> int:
+    return lib().mg_fp8_pack(_c(trans), R, K, X, ldx, q, scales, stream)
+
+
+def mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream) -> int:
+    return lib().mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream)
 
 
 def mg_num_configs(path) -> int:

@@ -30,9 +30,12 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the ROCm toolchain is required to build mgemm")
 
 
-# Packed-FP32 VALU instructions are disabled for all device code.
+# Packed-FP32 VALU instructions are disabled for all device code.  Private
+# arrays (staging registers) are never moved into LDS behind our back: the
+# kernels size their LDS explicitly.
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-disable-promote-alloca-to-lds",
                 "-Wall", "-Wno-unused-function"]
 
 

@@ -28,6 +28,19 @@ struct GemmArgs {
     int vec_a, vec_b, vec_c;   // 16-byte vector access allowed for A, B, C
 };
 
+// Arguments of the FP8 GEMM on packed operands (see gemm_fp8.hip).
+struct Fp8Args {
+    const uint8_t* qA;   // Mp x Kp E4M3 codes of op(A), row stride ldq
+    const uint8_t* qB;   // Np x Kp E4M3 codes of op(B)^T, row stride ldq
+    const uint8_t* sA;   // (Mp/128) x (Kp/128) E8M0 scale bytes, row stride lds
+    const uint8_t* sB;   // (Np/128) x (Kp/128)
+    float* C;
+    int64_t M, N, Kp;
+    int64_t ldq, lds, ldc;
+    float alpha, beta;
+    int tiles_m, tiles_n, group_m;
+};
+
 // Map a linear workgroup id to an output tile (tm, tn).
 //
 // Hardware hands consecutive workgroup ids to the 8 XCDs round-robin.  We

@@ -1,0 +1,306 @@
+// FP8 path: OCP E4M3 operands with one power-of-two FP32 scale per 128 x 128
+// tile, FP32 accumulation, on the scaled FP8 matrix cores of gfx950
+// (v_mfma_scale_f32_32x32x64_f8f6f4).
+//
+// Two stages, following Algorithm 1 of Kuzma et al. (SPE 2023):
+//
+// 1. Pack (fp8_pack_kernel).  Where the paper packs each block of A and B
+//    into a buffer in main memory in the micro-kernel's access order
+//    (Section 3.1), this stage packs all of op(A) (M x K) and op(B)^T (N x K)
+//    once into a caller-provided HBM workspace, quantised: for every
+//    128 x 128 tile, amax -> s = the smallest power of two with
+//    amax <= 448*s, q = E4M3(x / s) (x / s is exact: s is a power of two, and
+//    |x / s| <= 448 so no value saturates).  Rows are k-contiguous, rows are
+//    padded to a multiple of 256 and K to a multiple of 128 with zeros, so the
+//    GEMM needs no bounds checks on its loads.  The scale is kept as its
+//    E8M0 byte (exponent + 127).  One FP8 rank-4 update per 8-bit element
+//    group is Table 1's 8-bit row; gfx950's instruction is rank-64.
+//
+// 2. GEMM (gemm_fp8_kernel).  Workgroup tiles, an in-kernel loop over
+//    128-deep K-panels (one scale block per panel), packed panels copied into
+//    LDS with 16-byte loads, and a wave micro-kernel whose accumulators live
+//    for the whole K loop.  A wave's 32-row (32-column) MFMA block lies in one
+//    128-row tile of op(A) (op(B)^T), and each 64-deep K step lies in one
+//    128-deep scale block, so every lane of the wave passes the same scale
+//    byte to the scaled MFMA, which multiplies the block product by
+//    2^(ea-127) * 2^(eb-127) exactly before accumulating.
+//
+// Packed layout (also documented in include/mgemm.h):
+//   q:      Rp x Kp bytes, row r holds E4M3 codes of op(X)[r][0..Kp)
+//   scales: (Rp/128) x (Kp/128) E8M0 bytes, row-major
+//   Rp = roundup(R, 256), Kp = roundup(K, 128).
+#include "common.h"
+#include "kernels.h"
+
+namespace mg {
+
+constexpr int QT = 128;       // quantisation tile
+constexpr int QROW = 128 + 16; // LDS row of the transpose buffer (bytes)
+
+MG_DEVICE float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Smallest E with amax <= 448 * 2^E (E = 0 for amax == 0), clamped to the
+// E8M0 range; returned as the E8M0 byte E + 127.
+MG_DEVICE int scale_byte(float amax)
+{
+    if (!(amax > 0.f)) return 127;
+    int e;
+    const float f = frexpf(amax, &e);   // amax = f * 2^e, f in [0.5, 1); 448 = 0.875 * 2^9
+    int E = (f <= 0.875f) ? e - 9 : e - 8;
+    if (E < -127) E = -127;
+    if (E > 127) E = 127;
+    return E + 127;
+}
+
+MG_DEVICE floatx4 fetch4g(const float* __restrict__ src, int64_t ld, int64_t gr, int64_t gc,
+                          int64_t R, int64_t Cn, bool vec)
+{
+    floatx4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gr < R) {
+        const float* p = src + gr * ld + gc;
+        if (vec && gc + 3 < Cn) {
+            x = *reinterpret_cast<const floatx4*>(p);
+        } else {
+            if (gc + 0 < Cn) x[0] = p[0];
+            if (gc + 1 < Cn) x[1] = p[1];
+            if (gc + 2 < Cn) x[2] = p[2];
+            if (gc + 3 < Cn) x[3] = p[3];
+        }
+    }
+    return x;
+}
+
+// One workgroup of 256 threads per 128 x 128 tile of the logical R x Kd matrix
+// op(X).  T == false: X stored R x Kd (k contiguous); T == true: stored Kd x R.
+template <bool T>
+__global__ __launch_bounds__(256) void fp8_pack_kernel(const float* __restrict__ X, int64_t ldx,
+                                                       int64_t R, int64_t Kd, int vec,
+                                                       uint8_t* __restrict__ q, int64_t ldq,
+                                                       uint8_t* __restrict__ sc, int64_t lds)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[QT * QROW];
+    __shared__ float wmax[4];
+    const int tid = threadIdx.x;
+    const int64_t k0 = int64_t(blockIdx.x) * QT;
+    const int64_t r0 = int64_t(blockIdx.y) * QT;
+
+    // 16 chunks of 4 floats per thread.  Chunk id t + 256*s covers stored row
+    // id / 32 (of the tile) and stored columns 4*(id % 32) .. +3.
+    floatx4 v[16];
+    float amax = 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int id = tid + 256 * s;
+        const int sr = id / 32, scol = 4 * (id % 32);
+        v[s] = T ? fetch4g(X, ldx, k0 + sr, r0 + scol, Kd, R, vec)
+                 : fetch4g(X, ldx, r0 + sr, k0 + scol, R, Kd, vec);
+        amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v[s][0]), fabsf(v[s][1])),
+                                 fmaxf(fabsf(v[s][2]), fabsf(v[s][3]))));
+    }
+    amax = wave_max(amax);
+    if ((tid & 63) == 0) wmax[tid >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    const int sbyte = scale_byte(amax);
+    const float inv = __builtin_bit_cast(float, uint32_t(254 - sbyte) << 23);   // 2^-(sbyte-127)
+
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int id = tid + 256 * s;
+        const int sr = id / 32, scol = 4 * (id % 32);
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[s][0] * inv, v[s][1] * inv, 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(v[s][2] * inv, v[s][3] * inv, w, true);
+        if (!T) {
+            // stored row = logical row r, columns = k .. k+3
+            *reinterpret_cast<uint32_t*>(&tile[sr * QROW + scol]) = uint32_t(w);
+        } else {
+            // stored row = k, columns = four consecutive logical rows
+#pragma unroll
+            for (int b = 0; b < 4; ++b) tile[(scol + b) * QROW + sr] = uint8_t(uint32_t(w) >> (8 * b));
+        }
+    }
+    __syncthreads();
+    // Write the tile out: 128 rows x 128 bytes as 16-byte chunks.
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int id = tid + 256 * s;
+        const int r = id / 8, c = 16 * (id % 8);
+        *reinterpret_cast<uint4*>(q + (r0 + r) * ldq + k0 + c) =
+            *reinterpret_cast<const uint4*>(&tile[r * QROW + c]);
+    }
+    if (tid == 0) sc[blockIdx.y * lds + blockIdx.x] = uint8_t(sbyte);
+}
+
+hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, int64_t Kd, bool vec,
+                           uint8_t* q, int64_t ldq, uint8_t* sc, int64_t lds, int64_t Rp, int64_t Kp,
+                           hipStream_t stream)
+{
+    const dim3 grid(unsigned(Kp / QT), unsigned(Rp / QT)), block(256);
+    if (trans) hipLaunchKernelGGL(fp8_pack_kernel<true>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq, sc, lds);
+    else hipLaunchKernelGGL(fp8_pack_kernel<false>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq, sc, lds);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_fp8_kernel(Fp8Args g)
+{
+    constexpr int BK = 128;                 // one scale block per K-panel
+    constexpr int LDR = BK + 16;            // bytes per packed LDS row (padded)
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NT = (BM / WM) * WAVES_N * 64;
+    constexpr int V = WM / 32, H = WN / 32;
+    constexpr int CA = BM * BK / 16, CB = BN * BK / 16;   // 16-byte chunks per panel
+    static_assert(CA % NT == 0 && CB % NT == 0, "panels must split evenly");
+
+    __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * LDR];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LDR];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+    uint4 ra[CA / NT], rb[CB / NT];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int s = 0; s < CA / NT; ++s) {
+            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
+            ra[s] = *reinterpret_cast<const uint4*>(g.qA + (m0 + r) * g.ldq + k0 + cc);
+        }
+#pragma unroll
+        for (int s = 0; s < CB / NT; ++s) {
+            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
+            rb[s] = *reinterpret_cast<const uint4*>(g.qB + (n0 + r) * g.ldq + k0 + cc);
+        }
+    };
+    auto pack = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < CA / NT; ++s) {
+            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
+            *reinterpret_cast<uint4*>(&As[buf][r * LDR + cc]) = ra[s];
+        }
+#pragma unroll
+        for (int s = 0; s < CB / NT; ++s) {
+            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
+            *reinterpret_cast<uint4*>(&Bs[buf][r * LDR + cc]) = rb[s];
+        }
+    };
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int nk = int(g.Kp / BK);
+    fetch(0);
+    pack(0);
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) fetch(int64_t(kt + 1) * BK);
+
+        // wave-uniform E8M0 scale bytes of this K-panel for each MFMA block
+        int sa[V], sb[H];
+#pragma unroll
+        for (int i = 0; i < V; ++i) sa[i] = g.sA[((m0 + wm0 + 32 * i) / 128) * g.lds + kt];
+#pragma unroll
+        for (int j = 0; j < H; ++j) sb[j] = g.sB[((n0 + wn0 + 32 * j) / 128) * g.lds + kt];
+
+#pragma unroll
+        for (int s = 0; s < BK / 64; ++s) {
+            const int koff = 64 * s + 32 * h;
+            intx8 a[V], b[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const uint8_t* p = &As[cur][(wm0 + 32 * i + c) * LDR + koff];
+                const uint4 lo = *reinterpret_cast<const uint4*>(p);
+                const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+                a[i] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+            }
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const uint8_t* p = &Bs[cur][(wn0 + 32 * j + c) * LDR + koff];
+                const uint4 lo = *reinterpret_cast<const uint4*>(p);
+                const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+                b[j] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
+        }
+
+        if (more) pack(cur ^ 1);
+        __syncthreads();
+    }
+
+    const float alpha = g.alpha, beta = g.beta;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (m >= g.M) continue;
+            float* crow = g.C + m * g.ldc;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int64_t n = n0 + wn0 + 32 * j + c;
+                if (n < g.N) {
+                    float o = alpha * acc[i][j][r];
+                    if (beta != 0.f) o = __builtin_fmaf(alpha, acc[i][j][r], beta * crow[n]);
+                    crow[n] = o;
+                }
+            }
+        }
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_fp8_cfg(Fp8Args g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_fp8_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    return hipGetLastError();
+}
+
+const SgemmConfig kFp8Configs[] = {
+    // id, BM, BN, BK, WM, WN
+    {0, 256, 256, 128, 128, 128},
+    {1, 256, 128, 128, 128, 64},
+    {2, 128, 128, 128, 64, 64},
+    {3, 64, 64, 128, 32, 32},
+};
+const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
+
+hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
+{
+    switch (cfg) {
+    case 0: return launch_fp8_cfg<256, 256, 128, 128>(g, stream);
+    case 1: return launch_fp8_cfg<256, 128, 128, 64>(g, stream);
+    case 2: return launch_fp8_cfg<128, 128, 64, 64>(g, stream);
+    case 3: return launch_fp8_cfg<64, 64, 32, 32>(g, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mg

@@ -24,6 +24,14 @@ extern const int kNumBf16Configs;
 hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
 hipError_t launch_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
 
+extern const SgemmConfig kFp8Configs[];
+extern const int kNumFp8Configs;
+
+hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, int64_t Kd, bool vec,
+                           uint8_t* q, int64_t ldq, uint8_t* sc, int64_t lds, int64_t Rp, int64_t Kp,
+                           hipStream_t stream);
+hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream);
+
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
 }  // namespace mg

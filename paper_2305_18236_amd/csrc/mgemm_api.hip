@@ -57,6 +57,7 @@ ConfigTable table_of(int path)
     case MG_PATH_FP32: return {mg::kSgemmConfigs, mg::kNumSgemmConfigs};
     case MG_PATH_BF16X3:
     case MG_PATH_BF16: return {mg::kBf16Configs, mg::kNumBf16Configs};
+    case MG_PATH_FP8_T128: return {mg::kFp8Configs, mg::kNumFp8Configs};
     default: return {nullptr, 0};
     }
 }
@@ -73,10 +74,61 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         if (tiles(M, N, 128, 128) >= 128) return 0;
         return 3;
     }
+    if (path == MG_PATH_FP8_T128) {
+        if (tiles(M, N, 256, 256) >= 256) return 0;
+        if (tiles(M, N, 128, 128) >= 128) return 2;
+        return 3;
+    }
     if (tiles(M, N, 256, 256) >= 256) return 1;
     if (tiles(M, N, 256, 128) >= 256) return 3;
     if (tiles(M, N, 128, 128) >= 128) return 2;
     return 4;
+}
+
+// ---- FP8 packed layout: q is Rp x Kp bytes, scales (Rp/128) x (Kp/128) bytes.
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+int64_t fp8_rows(int64_t R) { return round_up(R > 0 ? R : 1, 256); }
+int64_t fp8_kp(int64_t K) { return round_up(K > 0 ? K : 1, 128); }
+size_t fp8_q_bytes(int64_t R, int64_t K) { return size_t(fp8_rows(R)) * size_t(fp8_kp(K)); }
+size_t fp8_s_bytes(int64_t R, int64_t K) { return size_t(fp8_rows(R) / 128) * size_t(fp8_kp(K) / 128); }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Fp8Workspace {
+    size_t qa, qb, sa, sb, total;
+};
+
+Fp8Workspace fp8_workspace(int64_t M, int64_t N, int64_t K)
+{
+    Fp8Workspace w{};
+    w.qa = 0;
+    w.qb = w.qa + align256(fp8_q_bytes(M, K));
+    w.sa = w.qb + align256(fp8_q_bytes(N, K));
+    w.sb = w.sa + align256(fp8_s_bytes(M, K));
+    w.total = w.sb + align256(fp8_s_bytes(N, K));
+    return w;
+}
+
+int run_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* qA, const uint8_t* sA,
+                   const uint8_t* qB, const uint8_t* sB, float beta, float* C, int64_t ldc,
+                   hipStream_t stream)
+{
+    int cfg = g_forced[MG_PATH_FP8_T128].load();
+    if (cfg < 0) cfg = choose_config(MG_PATH_FP8_T128, M, N, K);
+    mg::Fp8Args g{};
+    g.qA = qA; g.qB = qB; g.sA = sA; g.sB = sB; g.C = C;
+    g.M = M; g.N = N; g.Kp = fp8_kp(K);
+    g.ldq = g.Kp; g.lds = g.Kp / 128; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.group_m = 4;
+    return hip_status(mg::launch_gemm_fp8(cfg, g, stream));
+}
+
+int run_fp8_pack(bool trans, int64_t R, int64_t K, const float* X, int64_t ldx, uint8_t* q,
+                 uint8_t* sc, hipStream_t stream)
+{
+    const int64_t Rp = fp8_rows(R), Kp = fp8_kp(K);
+    const bool vec = aligned16(X) && ldx % 4 == 0;
+    return hip_status(mg::launch_fp8_pack(trans, X, ldx, R, K, vec, q, Kp, sc, Kp / 128, Rp, Kp, stream));
 }
 
 int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
@@ -113,16 +165,32 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
             const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
             int64_t ldc, void* workspace, size_t workspace_bytes, void* stream)
 {
-    (void)workspace;
-    (void)workspace_bytes;
     int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
     if (st != MG_OK) return st;
     if (table_of(path).n == 0) return MG_ERR_UNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (path == MG_PATH_FP8_T128) {
+        const size_t need = fp8_workspace(M, N, K).total;
+        if (M > 0 && N > 0 && K > 0 && alpha != 0.f &&
+            (workspace == nullptr || workspace_bytes < need ||
+             (reinterpret_cast<uintptr_t>(workspace) & 255) != 0))
+            return MG_ERR_WORKSPACE;
+    }
     if (M == 0 || N == 0) return MG_OK;
     if (K == 0 || alpha == 0.f) {
         if (beta == 1.f) return MG_OK;
         return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
+    }
+    if (path == MG_PATH_FP8_T128) {
+        const Fp8Workspace w = fp8_workspace(M, N, K);
+        uint8_t* base = static_cast<uint8_t*>(workspace);
+        st = run_fp8_pack(is_t(transA), M, K, A, lda, base + w.qa, base + w.sa, s);
+        if (st != MG_OK) return st;
+        // op(B)^T is N x K: stored as is when transB is 'T', transposed when 'N'.
+        st = run_fp8_pack(!is_t(transB), N, K, B, ldb, base + w.qb, base + w.sb, s);
+        if (st != MG_OK) return st;
+        return run_fp8_packed(M, N, K, alpha, base + w.qa, base + w.sa, base + w.qb, base + w.sb,
+                              beta, C, ldc, s);
     }
     return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
@@ -137,9 +205,55 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 
 size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
 {
-    (void)transA; (void)transB; (void)M; (void)N; (void)K;
-    (void)path;
-    return 0;
+    (void)transA; (void)transB;
+    if (path != MG_PATH_FP8_T128 || M <= 0 || N <= 0 || K <= 0) return 0;
+    return fp8_workspace(M, N, K).total;
+}
+
+int mg_fp8_packed_size(int64_t R, int64_t K, size_t* q_bytes, size_t* scale_bytes)
+{
+    if (R < 0) return -1;
+    if (K < 0) return -2;
+    if (q_bytes) *q_bytes = fp8_q_bytes(R, K);
+    if (scale_bytes) *scale_bytes = fp8_s_bytes(R, K);
+    return MG_OK;
+}
+
+int mg_fp8_pack(char trans, int64_t R, int64_t K, const float* X, int64_t ldx, uint8_t* q,
+                uint8_t* scales, void* stream)
+{
+    if (!is_n(trans) && !is_t(trans)) return -1;
+    if (R < 0) return -2;
+    if (K < 0) return -3;
+    if (X == nullptr && R > 0 && K > 0) return -4;
+    const int64_t cols = is_t(trans) ? R : K, rows = is_t(trans) ? K : R;
+    if (ldx < (cols > 1 ? cols : 1) || !fits(rows, ldx)) return -5;
+    if (q == nullptr) return -6;
+    if (scales == nullptr) return -7;
+    if (R > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    return run_fp8_pack(is_t(trans), R, K, X, ldx, q, scales, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mg_gemm_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* qA,
+                       const uint8_t* sA, const uint8_t* qB, const uint8_t* sB, float beta, float* C,
+                       int64_t ldc, void* stream)
+{
+    if (M < 0) return -1;
+    if (N < 0) return -2;
+    if (K < 0) return -3;
+    if (qA == nullptr || sA == nullptr) return -5;
+    if (qB == nullptr || sB == nullptr) return -7;
+    if (C == nullptr && M > 0 && N > 0) return -10;
+    if (ldc < (N > 1 ? N : 1) || !fits(M, ldc)) return -11;
+    if (M > INT_MAX || N > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    if ((reinterpret_cast<uintptr_t>(qA) & 15) || (reinterpret_cast<uintptr_t>(qB) & 15)) return -5;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (M == 0 || N == 0) return MG_OK;
+    if (K == 0 || alpha == 0.f) {
+        if (beta == 1.f) return MG_OK;
+        return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
+    }
+    return run_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, s);
 }
 
 int mg_num_configs(int path)
