@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["sgemm", "batched"], default="sgemm",
+                    help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -156,6 +158,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
+
+    if args.workload == "batched":
+        return bench_batched(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -219,6 +224,70 @@ def main():
         out["sampled_error_vs_fp64_oracle"] = {p: float(f"{e:.3e}") for p, e in errs.items()}
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, torch, si, native, dev):
+    """512 GEMMs with M, N, K log-uniform in [32, 2048] (multiples of 8), U[-1, 1]:
+    one persistent launch against one launch per problem."""
+    sizes = si.batched_sizes(512, si.seed_for(4, "A"))
+    ops = []
+    for i, (m, n, k) in enumerate(sizes):
+        A = torch.from_numpy(si.uniform((m, k), si.seed_for(4, "A", i))).to(dev)
+        B = torch.from_numpy(si.uniform((k, n), si.seed_for(4, "B", i))).to(dev)
+        ops.append((A, B, torch.zeros((m, n), device=dev)))
+    flops = sum(2.0 * m * n * k for m, n, k in sizes)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    out = {"metric": "uneven batched GEMM TFLOP/s, 512 problems in one persistent launch",
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "batched_uneven_512", "problems": 512,
+                      "sizes": "M,N,K log-uniform in [32, 2048], multiples of 8", "layout": "NN",
+                      "alpha": 1.0, "beta": 0.0, "total_gflop": round(flops / 1e9, 2)},
+           "paths": {}}
+    for path in ("fp32", "bf16x3"):
+        pid = {"fp32": 0, "bf16x3": 1}[path]
+        arr = (native.mg_problem * len(ops))()
+        for i, (A, B, C) in enumerate(ops):
+            m, k = A.shape
+            n = B.shape[1]
+            arr[i] = native.mg_problem(b"N", b"N", m, n, k, 1.0, 0.0, A.data_ptr(), k, B.data_ptr(), n,
+                                       C.data_ptr(), n)
+        need = native.mg_gemm_batched_workspace_size(pid, len(ops))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+        def persistent():
+            st, bad = native.mg_gemm_batched(pid, len(ops), arr, ws.data_ptr(), need, sp)
+            native.check(st, "mg_gemm_batched")
+
+        def per_problem():
+            for A, B, C in ops:
+                m, k = A.shape
+                n = B.shape[1]
+                native.check(native.mg_gemm(pid, "N", "N", m, n, k, 1.0, A.data_ptr(), k, B.data_ptr(), n,
+                                            0.0, C.data_ptr(), n, None, 0, sp), "mg_gemm")
+
+        res = {}
+        for name, fn in (("persistent", persistent), ("per_problem", per_problem)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            res[name] = {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                         "launches": 1 if name == "persistent" else len(ops)}
+        res["speedup_persistent_vs_per_problem"] = round(res["per_problem"]["ms"] / res["persistent"]["ms"], 3)
+        out["paths"][path] = res
+    out["value"] = out["paths"]["fp32"]["persistent"]["tflops"]
+    out["ms_per_step"] = out["paths"]["fp32"]["persistent"]["ms"]
+    out["dtype"] = "f32"
     print(json.dumps(out), flush=True)
 
 

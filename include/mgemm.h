@@ -70,6 +70,19 @@ enum mg_status {
     MG_ERR_HIP = -1000          /* MG_ERR_HIP - hipError_t                     */
 };
 
+/* One GEMM of a batch: the arguments of mg_sgemm (device pointers). */
+typedef struct mg_problem {
+    char transA, transB;
+    int64_t M, N, K;
+    float alpha, beta;
+    const float *A;
+    int64_t lda;
+    const float *B;
+    int64_t ldb;
+    float *C;
+    int64_t ldc;
+} mg_problem;
+
 /*
  * FP32 GEMM on the FP32 matrix cores (the paper's experiments are all FP32
  * SGEMM, Section 4).  Equivalent to mg_gemm(MG_PATH_FP32, ..., NULL, 0, stream).
@@ -109,6 +122,42 @@ int mg_config_info(int path, int index, int *out6);
  * return to automatic selection.  Process-wide; meant for the autotuner.
  */
 int mg_force_config(int path, int config_id);
+
+/*
+ * Tuning table written by the autotuner: text lines "path mb nb kb config",
+ * where mb/nb/kb are round(log2(M/N/K)) (0..20) and config an id from
+ * mg_config_info; '#' starts a comment.  A loaded table replaces the previous
+ * one; NULL clears it.  Selection order for every GEMM: mg_force_config, then
+ * the table, then the built-in rule.  Load it before launching GEMMs from
+ * other threads.  Returns MG_ERR_BAD_TABLE (previous table kept) for an
+ * unreadable or malformed file.
+ */
+int mg_load_tuning(const char *path);
+
+/* Configuration id a GEMM of this path and shape would use now. */
+int mg_tuned_config(int path, int64_t M, int64_t N, int64_t K);
+
+/*
+ * Uneven batched GEMM in ONE persistent kernel launch (paths FP32, BF16X3 and
+ * BF16).  problems: HOST array of `count` problems, each with the semantics
+ * and argument rules of mg_sgemm (quick returns included); problems must not
+ * write overlapping C.  Every problem is tiled with its own tile shape (chosen
+ * by the tuning table, else by its size), and one grid that fills the GPU
+ * walks the tiles of all problems, largest tiles first.
+ * workspace: device memory of at least mg_gemm_batched_workspace_size bytes,
+ * 256-byte aligned; it receives the problem descriptors (one host-to-device
+ * copy on `stream`, which may block the host until earlier work on the
+ * stream is done).
+ * Errors: -2 count < 0, -3 problems NULL; an invalid problem i returns its
+ * mg_sgemm code (-1 ... -13) and stores i in *bad_problem (if not NULL);
+ * MG_ERR_WORKSPACE; MG_ERR_UNSUPPORTED for MG_PATH_FP8_T128.
+ */
+size_t mg_gemm_batched_workspace_size(int path, int64_t count);
+/* Configuration id mg_gemm_batched would use for one problem of this shape. */
+int mg_batched_config(int path, int64_t M, int64_t N, int64_t K);
+int mg_gemm_batched(int path, int64_t count, const mg_problem *problems,
+                    void *workspace, size_t workspace_bytes, void *stream,
+                    int64_t *bad_problem);
 
 /*
  * The pack-stage conversion of the BF16 paths on its own (Table 1's bf16

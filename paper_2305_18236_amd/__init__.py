@@ -7,6 +7,8 @@ and streams; it computes nothing on the GEMM path.
 """
 from __future__ import annotations
 
+import os
+
 from . import _native
 from ._native import MgemmError, check, status_string  # noqa: F401
 
@@ -86,3 +88,41 @@ def gemm(A, B, C=None, *, alpha: float = 1.0, beta: float = 0.0, path="fp32", wo
                          float(beta), C.data_ptr(), ldc, ws_ptr, ws_bytes, _stream_ptr(A.device))
     check(st, "mg_gemm")
     return C
+
+
+def gemm_batched(problems, *, path="fp32", workspace=None):
+    """Run a list of GEMMs in ONE persistent kernel launch.
+
+    problems: iterable of (A, B, C, alpha, beta) with A (M x K), B (K x N)
+    float32 GPU tensors (row-major or transposed views) and C (M x N,
+    row-major) updated in place as C <- alpha*A@B + beta*C.
+    """
+    import torch
+    problems = list(problems)
+    arr = (_native.mg_problem * max(len(problems), 1))()
+    dev = None
+    for i, (A, B, C, alpha, beta) in enumerate(problems):
+        if A.dtype != torch.float32 or B.dtype != torch.float32 or C.dtype != torch.float32:
+            raise TypeError("operands must be float32")
+        M, K = A.shape
+        K2, N = B.shape
+        if K2 != K or tuple(C.shape) != (M, N):
+            raise ValueError(f"problem {i}: shapes {tuple(A.shape)} x {tuple(B.shape)} -> {tuple(C.shape)}")
+        if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
+            raise ValueError(f"problem {i}: C must have unit column stride")
+        tA, lda = operand_layout(A)
+        tB, ldb = operand_layout(B)
+        arr[i] = _native.mg_problem(tA.encode(), tB.encode(), M, N, K, float(alpha), float(beta),
+                                    A.data_ptr(), lda, B.data_ptr(), ldb, C.data_ptr(), max(C.stride(0), N, 1))
+        dev = A.device
+    if not problems:
+        return
+    pid = _path_id(path)
+    need = _native.mg_gemm_batched_workspace_size(pid, len(problems))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    st, bad = _native.mg_gemm_batched(pid, len(problems), arr, workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(), _stream_ptr(dev))
+    if st != 0 and bad >= 0:
+        raise MgemmError(st, f"mg_gemm_batched (problem {bad})")
+    check(st, "mg_gemm_batched")

@@ -16,6 +16,16 @@ LIB_PATH = os.path.join(_PKG, "libmgemm.so")
 _lib = None
 
 
+class mg_problem(ctypes.Structure):
+    """Mirror of struct mg_problem in include/mgemm.h."""
+    _fields_ = [("transA", ctypes.c_char), ("transB", ctypes.c_char),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
 class MgemmError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -53,10 +63,35 @@ def lib():
     L.mg_fp8_pack.restype = ci
     L.mg_gemm_fp8_packed.argtypes = [i64, i64, i64, f32, vp, vp, vp, vp, f32, vp, i64, vp]
     L.mg_gemm_fp8_packed.restype = ci
+    L.mg_load_tuning.argtypes = [ctypes.c_char_p]
+    L.mg_load_tuning.restype = ci
+    L.mg_tuned_config.argtypes = [ci, i64, i64, i64]
+    L.mg_tuned_config.restype = ci
+    L.mg_batched_config.argtypes = [ci, i64, i64, i64]
+    L.mg_batched_config.restype = ci
+    L.mg_gemm_batched_workspace_size.argtypes = [ci, i64]
+    L.mg_gemm_batched_workspace_size.restype = sz
+    L.mg_gemm_batched.argtypes = [ci, i64, ctypes.POINTER(mg_problem), vp, sz, vp,
+                                  ctypes.POINTER(i64)]
+    L.mg_gemm_batched.restype = ci
     L.mg_status_string.argtypes = [ci]
     L.mg_status_string.restype = ctypes.c_char_p
     _lib = L
+    _load_default_tuning(L)
     return L
+
+
+TUNING_TABLE = os.path.join(_PKG, "tuning_table.txt")
+
+
+def _load_default_tuning(L):
+    """Load the committed autotuner table (or $MGEMM_TUNING; "none" disables it)."""
+    path = os.environ.get("MGEMM_TUNING", TUNING_TABLE)
+    if path.lower() == "none" or not os.path.exists(path):
+        return
+    st = L.mg_load_tuning(os.fsencode(path))
+    if st != 0:
+        raise MgemmError(st, f"mg_load_tuning({path})")
 
 
 def _c(t) -> bytes:
@@ -103,6 +138,30 @@ def mg_fp8_pack(trans, R, K, X, ldx, q, scales, stream) -> int:
 
 def mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream) -> int:
     return lib().mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream)
+
+
+def mg_load_tuning(path) -> int:
+    return lib().mg_load_tuning(None if path is None else os.fsencode(path))
+
+
+def mg_tuned_config(path, M, N, K) -> int:
+    return int(lib().mg_tuned_config(int(path), M, N, K))
+
+
+def mg_batched_config(path, M, N, K) -> int:
+    return int(lib().mg_batched_config(int(path), M, N, K))
+
+
+def mg_gemm_batched_workspace_size(path, count) -> int:
+    return int(lib().mg_gemm_batched_workspace_size(int(path), int(count)))
+
+
+def mg_gemm_batched(path, count, problems, workspace, workspace_bytes, stream):
+    """problems: a ctypes array of mg_problem.  Returns (status, bad_problem index)."""
+    bad = ctypes.c_int64(-1)
+    st = lib().mg_gemm_batched(int(path), int(count), problems, workspace, workspace_bytes, stream,
+                               ctypes.byref(bad))
+    return int(st), int(bad.value)
 
 
 def mg_num_configs(path) -> int:

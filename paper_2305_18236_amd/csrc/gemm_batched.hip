@@ -1,0 +1,124 @@
+// Uneven batched GEMM in one persistent launch.
+//
+// Every problem of the batch is cut into output tiles of its own variant
+// (tile shape chosen per problem by the tuning table or the default rule),
+// the tiles of all problems form one work list, and a grid sized to fill the
+// GPU once walks that list with a fixed stride.  The host orders the problems
+// by the cost of one of their tiles, largest first, so the stride hands out
+// the long tiles first (longest-processing-time-first scheduling).
+//
+// Each tile runs the same layered tile code as the single-GEMM kernels
+// (tile_f32.h, tile_bf16.h): the blocked, packed, MFMA micro-kernel scheme of
+// Algorithm 1 of Kuzma et al. (SPE 2023), with one LDS buffer sized for the
+// largest variant shared by all of them.
+#include "tile_f32.h"
+#include "tile_bf16.h"
+#include "kernels.h"
+
+namespace mg {
+
+const int kSgemmBatchedCfg[kSgemmBatchedVariants] = {3, 0};
+const int kBf16BatchedCfg[kBf16BatchedVariants] = {4, 5, 2};
+
+// Index of the problem owning work item `item`: the last p with
+// tile_begin <= item (problems with no tiles are skipped by the search).
+MG_DEVICE int owner(const BatchProblem* __restrict__ P, int count, int64_t item)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P[mid].tile_begin <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+MG_DEVICE void f32_variant(const BatchProblem& p, int tm, int tn, float* smem)
+{
+    if (p.ta) {
+        if (p.tb) sgemm_tile<BM, BN, BK, WM, WN, true, true>(p.g, tm, tn, smem);
+        else sgemm_tile<BM, BN, BK, WM, WN, true, false>(p.g, tm, tn, smem);
+    } else {
+        if (p.tb) sgemm_tile<BM, BN, BK, WM, WN, false, true>(p.g, tm, tn, smem);
+        else sgemm_tile<BM, BN, BK, WM, WN, false, false>(p.g, tm, tn, smem);
+    }
+}
+
+// Two waves per SIMD: the register budget stays at 256 per lane, so two
+// workgroups share a CU and one's epilogue overlaps the other's K loop.
+__global__ __launch_bounds__(256, 2) void sgemm_batched_kernel(const BatchProblem* __restrict__ P, int count,
+                                                             int64_t total_tiles)
+{
+    __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<128, 128, 32>()];
+    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+        const BatchProblem& p = P[owner(P, count, item)];
+        const int64_t local = item - p.tile_begin;
+        const int tm = int(local / p.g.tiles_n), tn = int(local % p.g.tiles_n);
+        if (p.variant == 0) f32_variant<64, 64, 32, 32, 32>(p, tm, tn, smem);
+        else f32_variant<128, 128, 32, 64, 64>(p, tm, tn, smem);
+    }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int TERMS>
+MG_DEVICE void bf16_variant(const BatchProblem& p, int tm, int tn, uint16_t* smem)
+{
+    if (p.ta) {
+        if (p.tb) bf16_tile<BM, BN, BK, WM, WN, true, true, TERMS>(p.g, tm, tn, smem);
+        else bf16_tile<BM, BN, BK, WM, WN, true, false, TERMS>(p.g, tm, tn, smem);
+    } else {
+        if (p.tb) bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS>(p.g, tm, tn, smem);
+        else bf16_tile<BM, BN, BK, WM, WN, false, false, TERMS>(p.g, tm, tn, smem);
+    }
+}
+
+template <int TERMS>
+__global__ __launch_bounds__(256, 2) void bf16_batched_kernel(const BatchProblem* __restrict__ P, int count,
+                                                            int64_t total_tiles)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<128, 128, 32, TERMS>()];
+    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+        const BatchProblem& p = P[owner(P, count, item)];
+        const int64_t local = item - p.tile_begin;
+        const int tm = int(local / p.g.tiles_n), tn = int(local % p.g.tiles_n);
+        switch (p.variant) {
+        case 0: bf16_variant<64, 64, 32, 32, 32, TERMS>(p, tm, tn, smem); break;
+        case 1: bf16_variant<128, 64, 32, 64, 32, TERMS>(p, tm, tn, smem); break;
+        default: bf16_variant<128, 128, 32, 64, 64, TERMS>(p, tm, tn, smem); break;
+        }
+    }
+}
+
+static const void* batched_kernel(int path)
+{
+    switch (path) {
+    case 0: return reinterpret_cast<const void*>(&sgemm_batched_kernel);
+    case 1: return reinterpret_cast<const void*>(&bf16_batched_kernel<3>);
+    case 2: return reinterpret_cast<const void*>(&bf16_batched_kernel<1>);
+    default: return nullptr;
+    }
+}
+
+int batched_blocks_per_cu(int path)
+{
+    const void* k = batched_kernel(path);
+    if (!k) return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 256, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int count,
+                               int64_t total_tiles, int grid, hipStream_t stream)
+{
+    switch (path) {
+    case 0: hipLaunchKernelGGL(sgemm_batched_kernel, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
+    case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
+    case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mg

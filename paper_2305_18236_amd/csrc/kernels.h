@@ -32,6 +32,28 @@ hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, i
                            hipStream_t stream);
 hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream);
 
+// One problem of a batched launch, as the persistent kernel reads it.
+struct BatchProblem {
+    GemmArgs g;           // operands, sizes, strides, alpha/beta, tile grid, vector flags
+    int64_t tile_begin;   // first work item (tile) of this problem
+    int variant;          // tile variant of the path's batched set
+    int ta, tb;           // op(A) = A^T, op(B) = B^T
+    int pad_;
+};
+
+// Tile variants of the persistent batched kernels, as configuration ids of
+// the single-GEMM tables: FP32 {64x64, 128x128}; BF16 paths {64x64, 128x64,
+// 128x128}.  All run 256 threads.  (A third FP32 variant would push the
+// persistent kernel past 256 registers per lane.)
+constexpr int kSgemmBatchedVariants = 2;
+constexpr int kBf16BatchedVariants = 3;
+extern const int kSgemmBatchedCfg[kSgemmBatchedVariants];
+extern const int kBf16BatchedCfg[kBf16BatchedVariants];
+
+hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int count,
+                               int64_t total_tiles, int grid, hipStream_t stream);
+int batched_blocks_per_cu(int path);
+
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
 }  // namespace mg

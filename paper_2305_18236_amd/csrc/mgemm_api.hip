@@ -2,8 +2,13 @@
 // configuration choice (the blocking decision of Section 3.1) and launch on
 // the caller's stream.  Every check here runs on the host before any device
 // call, so invalid arguments never reach a kernel.
+#include <algorithm>
 #include <atomic>
 #include <climits>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "../../include/mgemm.h"
 #include "kernels.h"
@@ -62,6 +67,33 @@ ConfigTable table_of(int path)
     }
 }
 
+// ---- Tuning table: (path, bucket(M), bucket(N), bucket(K)) -> configuration
+// id, written by the autotuner.  bucket(x) = round(log2 x), clamped to
+// [0, kBuckets).  -1 means "not tuned".
+constexpr int kBuckets = 21;
+int8_t g_table[4][kBuckets][kBuckets][kBuckets];
+std::once_flag g_table_init;
+std::mutex g_table_mutex;
+
+void table_clear()
+{
+    std::memset(g_table, -1, sizeof(g_table));
+}
+
+int bucket(int64_t x)
+{
+    if (x <= 1) return 0;
+    int b = 63 - __builtin_clzll(uint64_t(x));
+    if (2 * x >= (int64_t(3) << b)) ++b;   // round to the nearer power of two
+    return b < kBuckets ? b : kBuckets - 1;
+}
+
+int table_lookup(int path, int64_t M, int64_t N, int64_t K)
+{
+    std::call_once(g_table_init, table_clear);
+    return g_table[path][bucket(M)][bucket(N)][bucket(K)];
+}
+
 // Automatic configuration: the largest workgroup tile that still gives every
 // compute unit at least one tile; smaller problems fall back to smaller tiles
 // so that more of the 256 CUs take part.
@@ -84,6 +116,8 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     if (tiles(M, N, 128, 128) >= 128) return 2;
     return 4;
 }
+
+int pick_config(int path, int64_t M, int64_t N, int64_t K);
 
 // ---- FP8 packed layout: q is Rp x Kp bytes, scales (Rp/128) x (Kp/128) bytes.
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -112,8 +146,7 @@ int run_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* 
                    const uint8_t* qB, const uint8_t* sB, float beta, float* C, int64_t ldc,
                    hipStream_t stream)
 {
-    int cfg = g_forced[MG_PATH_FP8_T128].load();
-    if (cfg < 0) cfg = choose_config(MG_PATH_FP8_T128, M, N, K);
+    const int cfg = pick_config(MG_PATH_FP8_T128, M, N, K);
     mg::Fp8Args g{};
     g.qA = qA; g.qB = qB; g.sA = sA; g.sB = sB; g.C = C;
     g.M = M; g.N = N; g.Kp = fp8_kp(K);
@@ -131,12 +164,21 @@ int run_fp8_pack(bool trans, int64_t R, int64_t K, const float* X, int64_t ldx, 
     return hip_status(mg::launch_fp8_pack(trans, X, ldx, R, K, vec, q, Kp, sc, Kp / 128, Rp, Kp, stream));
 }
 
+// forced > tuned > default rule
+int pick_config(int path, int64_t M, int64_t N, int64_t K)
+{
+    int cfg = g_forced[path].load();
+    if (cfg >= 0) return cfg;
+    cfg = table_lookup(path, M, N, K);
+    if (cfg >= 0 && cfg < table_of(path).n) return cfg;
+    return choose_config(path, M, N, K);
+}
+
 int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
              const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
              int64_t ldc, hipStream_t stream)
 {
-    int cfg = g_forced[path].load();
-    if (cfg < 0) cfg = choose_config(path, M, N, K);
+    const int cfg = pick_config(path, M, N, K);
     const ConfigTable t = table_of(path);
     const mg::SgemmConfig& c = t.cfgs[cfg];
     if (tiles(M, N, c.bm, c.bn) > INT_MAX) return MG_ERR_TOO_LARGE;
@@ -155,6 +197,49 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     case MG_PATH_BF16: return hip_status(mg::launch_gemm_bf16(1, cfg, ta, tb, g, stream));
     default: return MG_ERR_UNSUPPORTED;
     }
+}
+
+// ---- Batched: the tile variant of one problem (index into the batched set).
+const int* batched_cfgs(int path)
+{
+    return path == MG_PATH_FP32 ? mg::kSgemmBatchedCfg : mg::kBf16BatchedCfg;
+}
+
+int batched_count(int path)
+{
+    return path == MG_PATH_FP32 ? mg::kSgemmBatchedVariants : mg::kBf16BatchedVariants;
+}
+
+int choose_batched_variant(int path, int64_t M, int64_t N, int64_t K)
+{
+    const int* cfgs = batched_cfgs(path);
+    const int nv = batched_count(path);
+    int tuned = g_forced[path].load();
+    if (tuned < 0) tuned = table_lookup(path, M, N, K);
+    for (int v = 0; v < nv; ++v)
+        if (cfgs[v] == tuned) return v;
+    if (M >= 128 && N >= 128) return nv - 1;   // 128 x 128
+    if (M >= 128 && nv == 3) return 1;         // 128 x 64
+    return 0;                                  // 64 x 64
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+size_t batched_workspace(int64_t count)
+{
+    return count > 0 ? size_t(count) * sizeof(mg::BatchProblem) : 0;
 }
 
 }  // namespace
@@ -288,6 +373,126 @@ int mg_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* s
     if (x == nullptr) return -1;
     if (hi == nullptr) return -3;
     return hip_status(mg::launch_bf16_split(x, n, hi, lo, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int mg_load_tuning(const char* path)
+{
+    std::call_once(g_table_init, table_clear);
+    std::lock_guard<std::mutex> lock(g_table_mutex);
+    if (path == nullptr) {
+        table_clear();
+        return MG_OK;
+    }
+    FILE* f = std::fopen(path, "r");
+    if (!f) return MG_ERR_BAD_TABLE;
+    static int8_t fresh[4][kBuckets][kBuckets][kBuckets];
+    std::memset(fresh, -1, sizeof(fresh));
+    char line[256];
+    int bad = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        const char* q = line;
+        while (*q == ' ' || *q == '\t') ++q;
+        if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
+        int p, mb, nb, kb, cfg;
+        if (std::sscanf(q, "%d %d %d %d %d", &p, &mb, &nb, &kb, &cfg) != 5 || p < 0 || p > 3 ||
+            mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 || kb >= kBuckets ||
+            cfg < 0 || cfg >= table_of(p).n) {
+            bad = 1;
+            break;
+        }
+        fresh[p][mb][nb][kb] = int8_t(cfg);
+    }
+    std::fclose(f);
+    if (bad) return MG_ERR_BAD_TABLE;
+    std::memcpy(g_table, fresh, sizeof(g_table));
+    return MG_OK;
+}
+
+int mg_tuned_config(int path, int64_t M, int64_t N, int64_t K)
+{
+    if (path < 0 || path > 3 || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    return pick_config(path, M, N, K);
+}
+
+int mg_batched_config(int path, int64_t M, int64_t N, int64_t K)
+{
+    if (path < 0 || path > 2 || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    return batched_cfgs(path)[choose_batched_variant(path, M, N, K)];
+}
+
+size_t mg_gemm_batched_workspace_size(int path, int64_t count)
+{
+    if (path < 0 || path > 2) return 0;
+    return batched_workspace(count);
+}
+
+int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* workspace,
+                    size_t workspace_bytes, void* stream, int64_t* bad_problem)
+{
+    if (path < 0 || path > 2) return MG_ERR_UNSUPPORTED;
+    if (count < 0) return -2;
+    if (count > INT_MAX) return MG_ERR_TOO_LARGE;
+    if (count > 0 && problems == nullptr) return -3;
+    // validate every problem before touching the device
+    for (int64_t i = 0; i < count; ++i) {
+        const mg_problem& q = problems[i];
+        const int st = validate(q.transA, q.transB, q.M, q.N, q.K, q.A, q.lda, q.B, q.ldb, q.C, q.ldc);
+        if (st != MG_OK) {
+            if (bad_problem) *bad_problem = i;
+            return st;
+        }
+    }
+    if (count == 0) return MG_OK;
+    if (workspace == nullptr || workspace_bytes < batched_workspace(count) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return MG_ERR_WORKSPACE;
+
+    const ConfigTable t = table_of(path);
+    const int* cfgs = batched_cfgs(path);
+    std::vector<mg::BatchProblem> host;
+    std::vector<int64_t> cost;
+    host.reserve(size_t(count));
+    for (int64_t i = 0; i < count; ++i) {
+        const mg_problem& q = problems[i];
+        if (q.M == 0 || q.N == 0) continue;
+        mg::BatchProblem b{};
+        b.variant = choose_batched_variant(path, q.M, q.N, q.K);
+        const mg::SgemmConfig& c = t.cfgs[cfgs[b.variant]];
+        b.ta = is_t(q.transA);
+        b.tb = is_t(q.transB);
+        b.g.A = q.A; b.g.B = q.B; b.g.C = q.C;
+        b.g.M = q.M; b.g.N = q.N;
+        b.g.K = (q.alpha == 0.f) ? 0 : q.K;   // alpha == 0: A and B are not read
+        b.g.lda = q.lda; b.g.ldb = q.ldb; b.g.ldc = q.ldc;
+        b.g.alpha = q.alpha; b.g.beta = q.beta;
+        b.g.tiles_m = int((q.M + c.bm - 1) / c.bm);
+        b.g.tiles_n = int((q.N + c.bn - 1) / c.bn);
+        b.g.group_m = 1;
+        b.g.vec_a = aligned16(q.A) && q.lda % 4 == 0;
+        b.g.vec_b = aligned16(q.B) && q.ldb % 4 == 0;
+        b.g.vec_c = aligned16(q.C) && q.ldc % 4 == 0;
+        host.push_back(b);
+    }
+    if (host.empty()) return MG_OK;
+    // longest tiles first
+    std::stable_sort(host.begin(), host.end(), [&](const mg::BatchProblem& x, const mg::BatchProblem& y) {
+        const mg::SgemmConfig& cx = t.cfgs[cfgs[x.variant]];
+        const mg::SgemmConfig& cy = t.cfgs[cfgs[y.variant]];
+        return int64_t(cx.bm) * cx.bn * (x.g.K + 1) > int64_t(cy.bm) * cy.bn * (y.g.K + 1);
+    });
+    int64_t total = 0;
+    for (auto& b : host) {
+        b.tile_begin = total;
+        total += int64_t(b.g.tiles_m) * b.g.tiles_n;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size() * sizeof(mg::BatchProblem),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_status(e);
+    const int64_t slots = int64_t(device_cus()) * mg::batched_blocks_per_cu(path);
+    const int grid = int(std::min<int64_t>(total, slots));
+    return hip_status(mg::launch_gemm_batched(path, static_cast<const mg::BatchProblem*>(workspace),
+                                              int(host.size()), total, grid, s));
 }
 
 const char* mg_status_string(int status)

@@ -1,0 +1,284 @@
+#pragma once
+// GEMM on the BF16 matrix cores of gfx950 (v_mfma_f32_32x32x16_bf16) with FP32
+// inputs, outputs and accumulation.  Two arithmetic variants:
+//
+//   TERMS == 1  (plain BF16): each operand is rounded to bfloat16 (nearest,
+//               ties to even) while it is packed into LDS.
+//   TERMS == 3  (bf16x3 split): each operand x is split while packing into
+//               hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32),
+//               and the micro-kernel accumulates hi*hi + hi*lo + lo*hi in FP32;
+//               the dropped lo*lo term is below 2^-16 |a||b|.
+//
+// Layers follow Algorithm 1 of Kuzma et al. (SPE 2023) as in the FP32 kernel
+// (workgroup tiles for the i/j block loops, an in-kernel K-panel loop, packing
+// of op(A) and op(B) panels into LDS, a wave micro-kernel that keeps its
+// accumulators for the whole K loop).  Here the packing step also carries the
+// data-type conversion, the way Section 3's packing chooses the element layout
+// the target's matrix instruction wants: the rank-16 BF16 update reads eight
+// consecutive k of one row per lane (the 16-bit rank-n layout of Section 3.3,
+// scaled to the MFMA's depth), so both panels are packed k-contiguous:
+// row mn of a panel holds op(X)[mn][k0 .. k0+BK) as bf16, padded by PAD
+// elements so that the 16-byte fragment reads of consecutive rows fall in
+// different LDS banks.
+//
+// MFMA 32x32x16 bf16 operand layout: lane l supplies eight k values of
+// op(A) row l%32 and the same eight k values of op(B) column l%32 (k block
+// l/32); result register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32].
+#include "common.h"
+
+namespace mg {
+
+// Round two floats to bf16 (hardware RNE) and return them packed.
+MG_DEVICE uint32_t pack_bf16x2(float a, float b)
+{
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    bf16x2_t v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Split four floats: hi = bf16(x), lo = bf16(x - float(hi)).
+MG_DEVICE void split4(floatx4 x, uint32_t (&hi)[2], uint32_t (&lo)[2])
+{
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float x0 = x[2 * p], x1 = x[2 * p + 1];
+        const uint32_t h = pack_bf16x2(x0, x1);
+        const float h0 = __builtin_bit_cast(float, h << 16);
+        const float h1 = __builtin_bit_cast(float, h & 0xffff0000u);
+        hi[p] = h;
+        lo[p] = pack_bf16x2(x0 - h0, x1 - h1);
+    }
+}
+
+MG_DEVICE void round4(floatx4 x, uint32_t (&hi)[2])
+{
+    hi[0] = pack_bf16x2(x[0], x[1]);
+    hi[1] = pack_bf16x2(x[2], x[3]);
+}
+
+// Guarded 16-byte fetch of four consecutive stored columns (gc .. gc+3) of
+// stored row gr; out-of-range elements read 0.
+MG_DEVICE floatx4 fetch4(const float* __restrict__ src, int64_t ld, int64_t gr, int64_t gc,
+                         int64_t R, int64_t Cn, bool vec)
+{
+    floatx4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gr < R) {
+        const float* p = src + gr * ld + gc;
+        if (vec && gc + 3 < Cn) {
+            x = *reinterpret_cast<const floatx4*>(p);
+        } else {
+            if (gc + 0 < Cn) x[0] = p[0];
+            if (gc + 1 < Cn) x[1] = p[1];
+            if (gc + 2 < Cn) x[2] = p[2];
+            if (gc + 3 < Cn) x[3] = p[3];
+        }
+    }
+    return x;
+}
+
+// One operand panel: ROWS (m or n) x BK (k), FP32 in global memory, packed
+// into LDS as bf16 rows of LDR = BK + PAD elements.
+//   KSRC: the stored matrix is k-contiguous (A 'N', B 'T'); a chunk is four
+//         consecutive k of one row and becomes one 8-byte LDS write per term.
+//   else: the stored matrix is mn-contiguous (A 'T', B 'N'); a block is four
+//         k rows x four mn columns, fetched as four 16-byte loads and
+//         transposed in registers into four 8-byte LDS writes per term.
+template <int ROWS, int BK, int LDR, int NT, bool KSRC, int TERMS>
+struct BfPanel {
+    static constexpr int CHUNKS = ROWS * BK / 4;    // 16-byte chunks (KSRC)
+    static constexpr int BLOCKS = ROWS * BK / 16;   // 4x4 blocks (mn-contiguous source)
+    static constexpr int PER = KSRC ? (CHUNKS + NT - 1) / NT : (BLOCKS + NT - 1) / NT;
+    static constexpr int LOADS = KSRC ? PER : 4 * PER;
+    floatx4 v[LOADS];
+
+    // mn0: first row (m or n) of the panel; k0: first k.  R x Cn: valid extent
+    // of the stored matrix.
+    MG_DEVICE void load(const float* __restrict__ src, int64_t ld, int64_t mn0, int64_t k0,
+                        int64_t R, int64_t Cn, bool vec, int tid)
+    {
+        if (KSRC) {
+#pragma unroll
+            for (int s = 0; s < PER; ++s) {
+                const int q = tid + s * NT;
+                if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+                const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                v[s] = fetch4(src, ld, mn0 + r, k0 + c, R, Cn, vec);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const int q = tid + b * NT;
+                if (BLOCKS % NT != 0 && q >= BLOCKS) break;
+                const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[4 * b + e] = fetch4(src, ld, k0 + 4 * kb + e, mn0 + 4 * mb, R, Cn, vec);
+            }
+        }
+    }
+
+    MG_DEVICE void store(uint16_t* hi_lds, uint16_t* lo_lds, int tid) const
+    {
+        if (KSRC) {
+#pragma unroll
+            for (int s = 0; s < PER; ++s) {
+                const int q = tid + s * NT;
+                if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+                const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                put(hi_lds, lo_lds, r * LDR + c, v[s]);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const int q = tid + b * NT;
+                if (BLOCKS % NT != 0 && q >= BLOCKS) break;
+                const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const floatx4 col = {v[4 * b + 0][t], v[4 * b + 1][t], v[4 * b + 2][t], v[4 * b + 3][t]};
+                    put(hi_lds, lo_lds, (4 * mb + t) * LDR + 4 * kb, col);
+                }
+            }
+        }
+    }
+
+    MG_DEVICE static void put(uint16_t* hi_lds, uint16_t* lo_lds, int off, floatx4 x)
+    {
+        uint32_t h[2], l[2];
+        if (TERMS == 3) {
+            split4(x, h, l);
+            *reinterpret_cast<uint2*>(lo_lds + off) = make_uint2(l[0], l[1]);
+        } else {
+            round4(x, h);
+        }
+        *reinterpret_cast<uint2*>(hi_lds + off) = make_uint2(h[0], h[1]);
+    }
+};
+
+// Padding of a packed bf16 row (elements) and the LDS a configuration needs.
+constexpr int BF16_PAD = 8;
+template <int BM, int BN, int BK, int TERMS>
+constexpr int bf16_lds_elems() { return 2 * (TERMS == 3 ? 2 : 1) * (BM + BN) * (BK + BF16_PAD); }
+
+// One BM x BN output tile (tm, tn), computed by the whole workgroup.  smem:
+// bf16_lds_elems() 16-bit elements of LDS, 16-byte aligned.  Ends with a
+// workgroup barrier after the last LDS read.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int TERMS>
+MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
+{
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NT = (BM / WM) * WAVES_N * 64;
+    constexpr int V = WM / 32, H = WN / 32;
+    constexpr int LDR = BK + BF16_PAD;       // bf16 elements per packed row
+    constexpr int NL = (TERMS == 3) ? 2 : 1; // hi (and lo) panels
+    static_assert(BK % 16 == 0, "BK must be a multiple of the MFMA depth (16)");
+    static_assert((LDR * 2) % 16 == 0, "packed rows must keep 16-byte alignment");
+
+    uint16_t (*As)[NL][BM * LDR] = reinterpret_cast<uint16_t (*)[NL][BM * LDR]>(smem);
+    uint16_t (*Bs)[NL][BN * LDR] = reinterpret_cast<uint16_t (*)[NL][BN * LDR]>(smem + 2 * NL * BM * LDR);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+    BfPanel<BM, BK, LDR, NT, !TA, TERMS> pa;
+    BfPanel<BN, BK, LDR, NT, TB, TERMS> pb;
+    // Stored extents: A is M x K ('N') or K x M ('T'); B is K x N ('N') or N x K ('T').
+    const int64_t Ra = TA ? g.K : g.M, Ca = TA ? g.M : g.K;
+    const int64_t Rb = TB ? g.N : g.K, Cb = TB ? g.K : g.N;
+
+    auto fetch = [&](int64_t k0) {
+        pa.load(g.A, g.lda, m0, k0, Ra, Ca, g.vec_a, tid);
+        pb.load(g.B, g.ldb, n0, k0, Rb, Cb, g.vec_b, tid);
+    };
+    auto pack = [&](int buf) {
+        pa.store(As[buf][0], As[buf][NL - 1], tid);
+        pb.store(Bs[buf][0], Bs[buf][NL - 1], tid);
+    };
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int nk = int((g.K + BK - 1) / BK);
+    if (nk > 0) {
+        fetch(0);
+        pack(0);
+    }
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) fetch(int64_t(kt + 1) * BK);
+
+#pragma unroll
+        for (int s = 0; s < BK / 16; ++s) {
+            const int koff = 16 * s + 8 * h;
+            bf16x8 ah[V], bh[H], al[V], bl[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const int off = (wm0 + 32 * i + c) * LDR + koff;
+                ah[i] = *reinterpret_cast<const bf16x8*>(&As[cur][0][off]);
+                if (TERMS == 3) al[i] = *reinterpret_cast<const bf16x8*>(&As[cur][NL - 1][off]);
+            }
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int off = (wn0 + 32 * j + c) * LDR + koff;
+                bh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
+                if (TERMS == 3) bl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
+            }
+            if (TERMS == 3) {
+                // small terms first; consecutive instructions use different accumulators
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+
+        if (more) pack(cur ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: C = alpha*acc + beta*C0 (C0 not read when beta == 0).
+    const float alpha = g.alpha, beta = g.beta;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (m >= g.M) continue;
+            float* crow = g.C + m * g.ldc;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int64_t n = n0 + wn0 + 32 * j + c;
+                if (n < g.N) {
+                    float o = alpha * acc[i][j][r];
+                    if (beta != 0.f) o = __builtin_fmaf(alpha, acc[i][j][r], beta * crow[n]);
+                    crow[n] = o;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace mg

@@ -1,0 +1,253 @@
+#pragma once
+// FP32 GEMM tile on the FP32 matrix cores of gfx950 (v_mfma_f32_32x32x2_f32).
+//
+// This is the layered scheme of Kuzma et al. (SPE 2023), Algorithm 1, mapped
+// onto one GPU:
+//   * the j (nc) and i (mc) block loops become the workgroup grid: each
+//     workgroup owns one BM x BN tile of C (tile_of() orders the tiles so that
+//     concurrently running workgroups share panels in L2, the role the paper
+//     gives its L2/L3 blocking, Eq. 3-4);
+//   * the k (kc) loop becomes the in-kernel loop over BK-deep K-panels;
+//   * "pack A" / "pack B" (Algorithm 1, Section 3.1) become the copy of one
+//     BM x BK panel of op(A) and one BK x BN panel of op(B) from HBM into LDS,
+//     in the order the micro-kernel reads them.  The stored layout (N or T)
+//     only changes how the copy reads global memory: after packing every
+//     layout looks the same, which is how the paper absorbs transposition in
+//     the packing step.  Out-of-range rows, columns and K entries are packed as
+//     zeros (the remainder rule of Section 3.1);
+//   * the jj/ii/kk loops and the matrix intrinsic (Algorithm 2) become the
+//     wave micro-kernel: each wave keeps a WM x WN block of C in registers for
+//     the whole K loop as (WM/32) x (WN/32) accumulators of 32x32, and every
+//     operand register fetched from LDS feeds a whole row or column of
+//     accumulators (the VAccs x HAccs reuse of Algorithm 2);
+//   * the C update (Algorithm 1, after the kk loop) is fused into one epilogue
+//     C = alpha*acc + beta*C0 applied once after the full K, with C0 not read
+//     when beta == 0.
+//
+// Packed LDS layout.  Both panels are stored "k-major": row k of the A panel
+// holds the BM values op(A)[m0 .. m0+BM)[k], row k of the B panel the BN values
+// op(B)[k][n0 .. n0+BN).  A lane of a wave reads V = WM/32 consecutive floats of
+// one A row in one instruction; value j of lane c belongs to accumulator row
+// block j, row c, i.e. row m = wm0 + V*c + j (row blocks are interleaved).  The
+// same holds for B with H = WN/32.  The interleave makes each fragment read a
+// single 4*V-byte LDS access over contiguous addresses (no bank conflicts) and
+// lets the epilogue write H consecutive columns per lane.
+//
+// MFMA 32x32x2 f32 operand layout (per lane l of 64): A supplies
+// op(A)[row l%32][k l/32], B supplies op(B)[k l/32][col l%32]; result register
+// r of lane l is C[row 8*(r/4) + 4*(l/32) + r%4][col l%32].
+#include "common.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// Global -> register staging of one panel, in the stored layout.
+//
+// The stored panel is SR x SC floats (SR stored rows, SC stored columns, SC a
+// multiple of 4) starting at (r0, c0) of a stored matrix with R x Cn valid
+// entries and row stride ld.  Thread t fetches chunks q = t + s*NT, each four
+// consecutive stored columns of one stored row.  Out-of-range entries read 0.
+template <int SR, int SC, int NT>
+struct PanelLoader {
+    static constexpr int CHUNKS = SR * SC / 4;
+    static constexpr int PER_THREAD = (CHUNKS + NT - 1) / NT;
+    static_assert(CHUNKS % NT == 0, "panel must split evenly over the workgroup");
+
+    floatx4 v[PER_THREAD];
+
+    MG_DEVICE void load(const float* __restrict__ src, int64_t ld, int64_t r0, int64_t c0,
+                        int64_t R, int64_t Cn, bool vec, int tid)
+    {
+#pragma unroll
+        for (int s = 0; s < PER_THREAD; ++s) {
+            const int q = tid + s * NT;
+            const int r = q / (SC / 4);
+            const int c = (q % (SC / 4)) * 4;
+            const int64_t gr = r0 + r;
+            const int64_t gc = c0 + c;
+            floatx4 x = {0.f, 0.f, 0.f, 0.f};
+            if (gr < R) {
+                const float* p = src + gr * ld + gc;
+                if (vec && gc + 3 < Cn) {
+                    x = *reinterpret_cast<const floatx4*>(p);
+                } else {
+                    if (gc + 0 < Cn) x[0] = p[0];
+                    if (gc + 1 < Cn) x[1] = p[1];
+                    if (gc + 2 < Cn) x[2] = p[2];
+                    if (gc + 3 < Cn) x[3] = p[3];
+                }
+            }
+            v[s] = x;
+        }
+    }
+
+    // Write into a k-major LDS panel with row length L (floats).
+    // kmajor_src: the stored rows are k (stored columns are m or n), so a chunk
+    // is four consecutive m/n of one k row and is written as one 16-byte store.
+    // Otherwise the stored rows are m/n and a chunk is four consecutive k of
+    // one m/n: it is transposed into four 4-byte stores.
+    template <bool KMAJOR_SRC, int L>
+    MG_DEVICE void store(float* lds, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < PER_THREAD; ++s) {
+            const int q = tid + s * NT;
+            const int r = q / (SC / 4);
+            const int c = (q % (SC / 4)) * 4;
+            if (KMAJOR_SRC) {
+                *reinterpret_cast<floatx4*>(lds + r * L + c) = v[s];
+            } else {
+                lds[(c + 0) * L + r] = v[s][0];
+                lds[(c + 1) * L + r] = v[s][1];
+                lds[(c + 2) * L + r] = v[s][2];
+                lds[(c + 3) * L + r] = v[s][3];
+            }
+        }
+    }
+};
+
+template <int V>
+MG_DEVICE void lds_read(const float* p, float (&out)[V])
+{
+    if constexpr (V == 4) {
+        floatx4 t = *reinterpret_cast<const floatx4*>(p);
+        out[0] = t[0]; out[1] = t[1]; out[2] = t[2]; out[3] = t[3];
+    } else if constexpr (V == 2) {
+        floatx2 t = *reinterpret_cast<const floatx2*>(p);
+        out[0] = t[0]; out[1] = t[1];
+    } else {
+        out[0] = p[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS floats one tile configuration needs (two stages of both panels).
+template <int BM, int BN, int BK>
+constexpr int sgemm_lds_floats() { return 2 * BK * (BM + BN); }
+
+// One BM x BN output tile (tm, tn) of the GEMM in g, computed by the whole
+// workgroup ((BM/WM) * (BN/WN) waves).  smem: sgemm_lds_floats() floats of LDS,
+// 16-byte aligned.  Ends with a workgroup barrier after the last LDS read, so
+// the caller may reuse smem for another tile right away.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
+{
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NT = (BM / WM) * WAVES_N * 64;
+    constexpr int V = WM / 32;   // accumulator row blocks per wave
+    constexpr int H = WN / 32;   // accumulator column blocks per wave
+    static_assert(V == 1 || V == 2 || V == 4, "WM must be 32, 64 or 128");
+    static_assert(H == 1 || H == 2 || H == 4, "WN must be 32, 64 or 128");
+    static_assert(BK % 2 == 0, "BK must be a multiple of the MFMA depth");
+
+    float (*As)[BK * BM] = reinterpret_cast<float (*)[BK * BM]>(smem);
+    float (*Bs)[BK * BN] = reinterpret_cast<float (*)[BK * BN]>(smem + 2 * BK * BM);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM;
+    const int wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31;     // column of the MFMA operand / result
+    const int h = lane >> 5;     // which k of the pair this lane supplies
+
+    const int64_t m0 = int64_t(tm) * BM;
+    const int64_t n0 = int64_t(tn) * BN;
+
+    // Stored panels: A is M x K ('N') or K x M ('T'); B is K x N ('N') or N x K ('T').
+    using LA = PanelLoader<TA ? BK : BM, TA ? BM : BK, NT>;
+    using LB = PanelLoader<TB ? BN : BK, TB ? BK : BN, NT>;
+    LA la;
+    LB lb;
+    const int64_t Ra = TA ? g.K : g.M, Ca = TA ? g.M : g.K;
+    const int64_t Rb = TB ? g.N : g.K, Cb = TB ? g.K : g.N;
+
+    auto fetch = [&](int64_t k0) {
+        if (TA) la.load(g.A, g.lda, k0, m0, Ra, Ca, g.vec_a, tid);
+        else    la.load(g.A, g.lda, m0, k0, Ra, Ca, g.vec_a, tid);
+        if (TB) lb.load(g.B, g.ldb, n0, k0, Rb, Cb, g.vec_b, tid);
+        else    lb.load(g.B, g.ldb, k0, n0, Rb, Cb, g.vec_b, tid);
+    };
+    auto pack = [&](int buf) {
+        la.template store<TA, BM>(As[buf], tid);
+        lb.template store<!TB, BN>(Bs[buf], tid);
+    };
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int nk = int((g.K + BK - 1) / BK);
+    if (nk > 0) {
+        fetch(0);
+        pack(0);
+    }
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) fetch(int64_t(kt + 1) * BK);
+
+        const float* a_base = As[cur] + wm0 + V * c;
+        const float* b_base = Bs[cur] + wn0 + H * c;
+#pragma unroll
+        for (int s = 0; s < BK / 2; ++s) {
+            const int k = 2 * s + h;
+            float a[V], b[H];
+            lds_read<V>(a_base + k * BM, a);
+            lds_read<H>(b_base + k * BN, b);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = mfma_f32_32x32x2(a[i], b[j], acc[i][j]);
+        }
+
+        if (more) pack(cur ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: C = alpha*acc + beta*C0, once per element.
+    const float alpha = g.alpha, beta = g.beta;
+    const int64_t ncol = n0 + wn0 + H * c;   // first of this lane's H columns
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row_in_block = 8 * (r >> 2) + 4 * h + (r & 3);
+            const int64_t m = m0 + wm0 + V * row_in_block + i;
+            if (m >= g.M) continue;
+            float* cp = g.C + m * g.ldc + ncol;
+            float out[H];
+#pragma unroll
+            for (int j = 0; j < H; ++j) out[j] = acc[i][j][r];
+            if (H == 4 && g.vec_c && ncol + 3 < g.N) {
+                floatx4 o = {alpha * out[0], alpha * out[1], alpha * out[2], alpha * out[3]};
+                if (beta != 0.f) {
+                    const floatx4 c0 = *reinterpret_cast<const floatx4*>(cp);
+                    o[0] = __builtin_fmaf(alpha, out[0], beta * c0[0]);
+                    o[1] = __builtin_fmaf(alpha, out[1], beta * c0[1]);
+                    o[2] = __builtin_fmaf(alpha, out[2], beta * c0[2]);
+                    o[3] = __builtin_fmaf(alpha, out[3], beta * c0[3]);
+                }
+                *reinterpret_cast<floatx4*>(cp) = o;
+            } else {
+#pragma unroll
+                for (int j = 0; j < H; ++j) {
+                    if (ncol + j < g.N) {
+                        float o = alpha * out[j];
+                        if (beta != 0.f) o = __builtin_fmaf(alpha, out[j], beta * cp[j]);
+                        cp[j] = o;
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace mg

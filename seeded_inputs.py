@@ -82,7 +82,7 @@ def store(logical: np.ndarray, trans: str, ld: int | None = None) -> tuple[np.nd
     """
     phys = logical if trans in "Nn" else logical.T
     rows, cols = phys.shape
-    ld = cols if ld is None else int(ld)
+    ld = max(cols, 1) if ld is None else int(ld)
     if ld < max(1, cols):
         raise ValueError("ld smaller than the stored row length")
     buf = np.full((max(rows, 1), ld), np.nan, dtype=np.float32)

@@ -49,14 +49,29 @@ class Problem:
             self.C0 = gen((M, N), seed * 10 + 2)
         self.A, self.lda = si.store(self.opA, tA, lda)
         self.B, self.ldb = si.store(self.opB, tB, ldb)
-        self.ldc = N if ldc is None else ldc
+        self.ldc = max(N, 1) if ldc is None else ldc
         Cbuf = np.full((max(M, 1), max(self.ldc, 1)), -7.0, np.float32)
         Cbuf[:M, :N] = self.C0
         self.Cbuf = Cbuf.reshape(-1)
 
+    @classmethod
+    def from_arrays(cls, opA, opB, C0=None, alpha=1.0, beta=0.0, tA="N", tB="N"):
+        """A problem on given logical operands (C0 defaults to zeros)."""
+        p = cls.__new__(cls)
+        p.M, p.K = opA.shape
+        p.N = opB.shape[1]
+        p.tA, p.tB, p.alpha, p.beta = tA, tB, alpha, beta
+        p.opA, p.opB = opA, opB
+        p.C0 = np.zeros((p.M, p.N), np.float32) if C0 is None else C0
+        p.A, p.lda = si.store(opA, tA)
+        p.B, p.ldb = si.store(opB, tB)
+        p.ldc = max(p.N, 1)
+        p.Cbuf = np.ascontiguousarray(p.C0, np.float32).reshape(-1)
+        return p
+
     def oracle(self, threads=None):
         return oracle.gemm(self.tA, self.tB, self.M, self.N, self.K, self.alpha, self.A, self.lda,
-                           self.B, self.ldb, self.beta, self.C0, self.N, threads=threads)
+                           self.B, self.ldb, self.beta, self.C0, max(self.N, 1), threads=threads)
 
     def oracle_entries(self, I, J, threads=None):
         return oracle.gemm_entries(self.tA, self.tB, self.K, self.alpha, self.A, self.lda, self.B,

@@ -1,0 +1,112 @@
+"""Host-side checks of the tuning table and of batched-argument validation
+(no device call is made by anything tested here)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2305_18236_amd import autotune
+
+
+@pytest.fixture()
+def native():
+    from paper_2305_18236_amd import _native
+    _native.lib()
+    yield _native
+    # restore the default table
+    _native.mg_load_tuning(None)
+    _native._load_default_tuning(_native.lib())
+
+
+def test_bucket_rule_matches_library(native, tmp_path):
+    # a table that maps every (mb, nb, kb) of path 0 to a config derived from mb
+    n = native.mg_num_configs(0)
+    lines = [f"0 {mb} {nb} {kb} {mb % n}" for mb in range(21) for nb in (10,) for kb in (10,)]
+    p = tmp_path / "t.txt"
+    p.write_text("# test\n" + "\n".join(lines) + "\n")
+    assert native.mg_load_tuning(str(p)) == 0
+    for M in [1, 2, 3, 5, 6, 7, 11, 12, 13, 23, 24, 25, 95, 96, 97, 1000, 1536, 1535, 3000, 10 ** 6, 10 ** 9]:
+        assert native.mg_tuned_config(0, M, 1024, 1024) == autotune.bucket(M) % n, M
+
+
+def test_table_selection_order(native, tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text("0 8 8 8 3\n1 8 8 8 2\n")
+    assert native.mg_load_tuning(str(p)) == 0
+    assert native.mg_tuned_config(0, 256, 256, 256) == 3
+    assert native.mg_tuned_config(1, 256, 256, 256) == 2
+    # forced configuration wins over the table
+    assert native.mg_force_config(0, 1) == 0
+    try:
+        assert native.mg_tuned_config(0, 256, 256, 256) == 1
+    finally:
+        native.mg_force_config(0, -1)
+    # untuned buckets use the built-in rule: the same as with no table at all
+    untuned = native.mg_tuned_config(0, 8192, 8192, 8192)
+    native.mg_load_tuning(None)
+    assert native.mg_tuned_config(0, 8192, 8192, 8192) == untuned
+
+
+@pytest.mark.parametrize("text", ["0 8 8 8\n", "0 8 8 8 99\n", "7 8 8 8 0\n", "0 30 8 8 0\n", "x y z\n"])
+def test_malformed_table_rejected_and_previous_kept(native, tmp_path, text):
+    good = tmp_path / "good.txt"
+    good.write_text("0 8 8 8 3\n")
+    assert native.mg_load_tuning(str(good)) == 0
+    bad = tmp_path / "bad.txt"
+    bad.write_text(text)
+    assert native.mg_load_tuning(str(bad)) == -103
+    assert native.mg_tuned_config(0, 256, 256, 256) == 3
+
+
+def test_missing_table_file(native, tmp_path):
+    assert native.mg_load_tuning(str(tmp_path / "nope.txt")) == -103
+
+
+def test_committed_table_parses(native):
+    path = native.TUNING_TABLE
+    if not os.path.exists(path):
+        pytest.skip("no tuning table committed")
+    assert native.mg_load_tuning(path) == 0
+
+
+def test_autotune_pruning():
+    # 64 x 64 tiles never waste more than 4x area; 256 x 256 tiles on a 40 x 40 problem do
+    assert autotune.padded_area_ratio(40, 40, 64, 64) <= 4.0
+    assert autotune.padded_area_ratio(40, 40, 256, 256) > 4.0
+
+
+FAKE = 0x1000
+
+
+def _problem(native, **kw):
+    a = dict(transA=b"N", transB=b"N", M=4, N=5, K=6, alpha=1.0, beta=0.0, A=FAKE, lda=6,
+             B=FAKE, ldb=5, C=FAKE, ldc=5)
+    a.update(kw)
+    return native.mg_problem(a["transA"], a["transB"], a["M"], a["N"], a["K"], a["alpha"], a["beta"],
+                             a["A"], a["lda"], a["B"], a["ldb"], a["C"], a["ldc"])
+
+
+def test_batched_validation_reports_the_bad_problem(native):
+    arr = (native.mg_problem * 4)(_problem(native), _problem(native), _problem(native, ldb=2),
+                                  _problem(native, transA=b"Q"))
+    st, bad = native.mg_gemm_batched(0, 4, arr, FAKE, 1 << 20, None)
+    assert (st, bad) == (-10, 2)
+    st, bad = native.mg_gemm_batched(0, -1, arr, FAKE, 1 << 20, None)
+    assert st == -2
+    st, bad = native.mg_gemm_batched(3, 4, arr, FAKE, 1 << 20, None)
+    assert st == -101
+    # valid problems but no workspace: rejected before any device call
+    ok = (native.mg_problem * 2)(_problem(native), _problem(native))
+    st, bad = native.mg_gemm_batched(0, 2, ok, None, 0, None)
+    assert st == -100
+    assert native.mg_gemm_batched_workspace_size(0, 2) > 0
+    assert native.mg_gemm_batched_workspace_size(3, 2) == 0
+    # an all-empty batch is a no-op
+    empty = (native.mg_problem * 2)(_problem(native, M=0, A=None, C=None), _problem(native, N=0, B=None, C=None, ldb=1, ldc=1))
+    st, bad = native.mg_gemm_batched(0, 2, empty, FAKE, 1 << 20, None)
+    assert st == 0
+
+
+def test_problem_struct_layout(native):
+    # the C struct has natural alignment: char, char, pad, 3 x int64, 2 x float, 6 x (ptr/int64)
+    assert ctypes.sizeof(native.mg_problem) == 8 + 24 + 8 + 48
