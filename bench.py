@@ -134,8 +134,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched"], default="sgemm",
-                    help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems")
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain"], default="sgemm",
+                    help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
+                         "chain: forward + backward of Y = (X W1) W2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,6 +162,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args, torch, si, native, dev)
+    if args.workload == "chain":
+        return bench_chain(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -288,6 +291,53 @@ def bench_batched(args, torch, si, native, dev):
     out["value"] = out["paths"]["fp32"]["persistent"]["tflops"]
     out["ms_per_step"] = out["paths"]["fp32"]["persistent"]["ms"]
     out["dtype"] = "f32"
+    print(json.dumps(out), flush=True)
+
+
+def bench_chain(args, torch, si, native, dev):
+    """Y = (X W1) W2 with X 4096x2048, W1 2048x8192, W2 8192x2048; one step is
+    the forward (2 GEMMs) and the hand-written backward (4 GEMMs) of
+    loss = sum(Y * G), on the bf16x3 path and on the FP32 path."""
+    from paper_2305_18236_amd.autograd import chain
+    Mx, D, Hd = 4096, 2048, 8192
+    X = torch.from_numpy(si.uniform((Mx, D), si.seed_for(5, "X"))).to(dev).requires_grad_(True)
+    W1 = torch.from_numpy(si.uniform((D, Hd), si.seed_for(5, "W1"))).to(dev).requires_grad_(True)
+    W2 = torch.from_numpy(si.uniform((Hd, D), si.seed_for(5, "W2"))).to(dev).requires_grad_(True)
+    G = torch.from_numpy(si.gaussian((Mx, D), si.seed_for(5, "G"))).to(dev)
+    gemm_flop = 2.0 * Mx * D * Hd
+    flops = 6 * gemm_flop
+    out = {"metric": "differentiable GEMM chain TFLOP/s (forward + hand-written backward)",
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "gemm_chain_4096x2048x8192", "X": [Mx, D], "W1": [D, Hd], "W2": [Hd, D],
+                      "loss": "sum(Y*G), G ~ N(0,1)", "gemms_per_step": 6,
+                      "gflop_per_step": round(flops / 1e9, 1)},
+           "paths": {}}
+    stream = torch.cuda.current_stream()
+    for path in ("bf16x3", "fp32"):
+        def step():
+            for t in (X, W1, W2):
+                t.grad = None
+            Y = chain(X, W1, W2, path)
+            Y.backward(G)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out["paths"][path] = {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
+    b, f = out["paths"]["bf16x3"], out["paths"]["fp32"]
+    out["value"] = b["tflops"]
+    out["ms_per_step"] = b["ms_per_step"]
+    out["dtype"] = "bf16x3"
+    out["speedup_bf16x3_vs_fp32"] = round(f["ms_per_step"] / b["ms_per_step"], 3)
     print(json.dumps(out), flush=True)
 
 

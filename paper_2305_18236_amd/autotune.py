@@ -12,9 +12,11 @@ than 4x its area, i.e. waste three quarters of the matrix-core work).
 Buckets are round(log2) of M, N and K, the same rule the C library uses to
 read the table.  Two modes:
   batched: candidates are the tile variants of the persistent batched kernel;
-           each is timed on a batch of copies of the bucket's representative
-           shape, inside the persistent kernel (where launch overhead cannot
-           hide differences);
+           each is timed inside the persistent kernel on a batch of copies of
+           the bucket's representative shape, with enough copies for about
+           four 128 x 128 tiles per workgroup slot of the GPU, i.e. in the
+           saturated regime a large uneven batch runs in (a lone problem
+           would favour small tiles just to occupy more compute units);
   single:  candidates are all configurations of the path, timed on one GEMM.
 
 Usage (on a GPU):
@@ -32,6 +34,7 @@ import time
 from . import _native
 
 PATH_IDS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+SLOTS = 512          # workgroup slots of the persistent kernel: 256 CUs x 2
 BATCHED_CFGS = {0: [3, 0], 1: [4, 5, 2], 2: [4, 5, 2]}
 
 
@@ -67,11 +70,14 @@ class _Bench:
         self.dev = dev
 
     def operands(self, M, N, K, copies):
+        """`copies` problems sharing one A and one B, each with its own slice of C."""
         t = self.torch
         g = t.Generator(device=self.dev)
         g.manual_seed(M * 7919 + N * 31 + K)
-        mk = lambda r, c: (t.rand((r, c), device=self.dev, generator=g) * 2 - 1)
-        return [(mk(M, K), mk(K, N), t.zeros((M, N), device=self.dev)) for _ in range(copies)]
+        A = t.rand((M, K), device=self.dev, generator=g) * 2 - 1
+        B = t.rand((K, N), device=self.dev, generator=g) * 2 - 1
+        C = t.zeros((copies, M, N), device=self.dev)
+        return [(A, B, C[i]) for i in range(copies)]
 
     def time(self, fn, reps):
         t = self.torch
@@ -105,7 +111,8 @@ def tune(paths=("fp32", "bf16x3", "bf16"), mode="batched", buckets=range(5, 12),
             for nb in buckets:
                 for kb in buckets:
                     M, N, K = 2 ** mb, 2 ** nb, 2 ** kb
-                    copies = 1 if mode == "single" else int(min(64, max(1, math.ceil(2e9 / (2.0 * M * N * K)))))
+                    tiles128 = math.ceil(M / 128) * math.ceil(N / 128)
+                    copies = 1 if mode == "single" else int(min(4096, max(1, math.ceil(4 * SLOTS / tiles128))))
                     ops = bench.operands(M, N, K, copies)
                     best, best_t = None, float("inf")
                     for cid in candidates(pid, mode, M, N):
