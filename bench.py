@@ -106,7 +106,7 @@ def single_result(path, A, B, C0_dev, torch, native):
     return C
 
 
-def cpu_baseline(A_h, B_h, C0_h, gpu_rows, target_s=12.0):
+def cpu_baseline(A_h, B_h, C0_h, gpu_rows, target_s=25.0):
     """Time the FP64 oracle on a block of output rows of the same GEMM, and
     score the GPU results on those rows."""
     import oracle
