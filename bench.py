@@ -206,7 +206,7 @@ def main():
         "pct_fp32_mfma_peak": round(100.0 * f32["tflops"] / peak, 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "sgemm_mfma_kernel<256,256,16,128,128,NN>",
+                     "kernel": "sgemm_mfma_kernel<256,256,16,128,64,NN>",
                      "kernel_ms_mean": round(f32["kernel_ms_mean"], 4),
                      "algorithmic_flops_per_launch": flops},
     }

@@ -65,6 +65,27 @@ MG_DEVICE void tile_of(int pid, int tiles_m, int tiles_n, int group_m, int& tm, 
     tn = local / rows;
 }
 
+// Guarded 16-byte fetch of stored columns gc .. gc+3 of stored row gr of a
+// matrix with R x Cn valid entries (row stride ld); out-of-range elements read
+// 0.  Used only on edge panels: its per-lane branches serialise the loads.
+MG_DEVICE floatx4 fetch4_guarded(const float* __restrict__ src, int64_t ld, int64_t gr, int64_t gc,
+                                 int64_t R, int64_t Cn, bool vec)
+{
+    floatx4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gr < R) {
+        const float* p = src + gr * ld + gc;
+        if (vec && gc + 3 < Cn) {
+            x = *reinterpret_cast<const floatx4*>(p);
+        } else {
+            if (gc + 0 < Cn) x[0] = p[0];
+            if (gc + 1 < Cn) x[1] = p[1];
+            if (gc + 2 < Cn) x[2] = p[2];
+            if (gc + 3 < Cn) x[3] = p[3];
+        }
+    }
+    return x;
+}
+
 MG_DEVICE floatx16 mfma_f32_32x32x2(float a, float b, floatx16 c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);

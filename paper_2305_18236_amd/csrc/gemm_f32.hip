@@ -39,6 +39,9 @@ const SgemmConfig kSgemmConfigs[] = {
     {2, 256, 128, 32, 128, 64},
     {3, 64, 64, 32, 32, 32},
     {4, 128, 64, 32, 64, 32},
+    {5, 256, 256, 16, 128, 64},
+    {6, 256, 256, 32, 128, 64},
+    {7, 256, 256, 32, 128, 128},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -50,6 +53,9 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 2: return launch_sgemm_cfg<256, 128, 32, 128, 64>(ta, tb, g, stream);
     case 3: return launch_sgemm_cfg<64, 64, 32, 32, 32>(ta, tb, g, stream);
     case 4: return launch_sgemm_cfg<128, 64, 32, 64, 32>(ta, tb, g, stream);
+    case 5: return launch_sgemm_cfg<256, 256, 16, 128, 64>(ta, tb, g, stream);
+    case 6: return launch_sgemm_cfg<256, 256, 32, 128, 64>(ta, tb, g, stream);
+    case 7: return launch_sgemm_cfg<256, 256, 32, 128, 128>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

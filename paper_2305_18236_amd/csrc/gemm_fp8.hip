@@ -57,24 +57,6 @@ MG_DEVICE int scale_byte(float amax)
     return E + 127;
 }
 
-MG_DEVICE floatx4 fetch4g(const float* __restrict__ src, int64_t ld, int64_t gr, int64_t gc,
-                          int64_t R, int64_t Cn, bool vec)
-{
-    floatx4 x = {0.f, 0.f, 0.f, 0.f};
-    if (gr < R) {
-        const float* p = src + gr * ld + gc;
-        if (vec && gc + 3 < Cn) {
-            x = *reinterpret_cast<const floatx4*>(p);
-        } else {
-            if (gc + 0 < Cn) x[0] = p[0];
-            if (gc + 1 < Cn) x[1] = p[1];
-            if (gc + 2 < Cn) x[2] = p[2];
-            if (gc + 3 < Cn) x[3] = p[3];
-        }
-    }
-    return x;
-}
-
 // One workgroup of 256 threads per 128 x 128 tile of the logical R x Kd matrix
 // op(X).  T == false: X stored R x Kd (k contiguous); T == true: stored Kd x R.
 template <bool T>
@@ -92,16 +74,28 @@ __global__ __launch_bounds__(256) void fp8_pack_kernel(const float* __restrict__
     // 16 chunks of 4 floats per thread.  Chunk id t + 256*s covers stored row
     // id / 32 (of the tile) and stored columns 4*(id % 32) .. +3.
     floatx4 v[16];
+    // stored tile origin and valid extent
+    const int64_t sr0 = T ? k0 : r0, sc0 = T ? r0 : k0;
+    const int64_t SRn = T ? Kd : R, SCn = T ? R : Kd;
+    if (vec && sr0 + QT <= SRn && sc0 + QT <= SCn) {   // wave-uniform: interior tile
+        const float* __restrict__ base = X + sr0 * ldx + sc0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int id = tid + 256 * s;
+            v[s] = *reinterpret_cast<const floatx4*>(base + (id / 32) * ldx + 4 * (id % 32));
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int id = tid + 256 * s;
+            v[s] = fetch4_guarded(X, ldx, sr0 + id / 32, sc0 + 4 * (id % 32), SRn, SCn, vec);
+        }
+    }
     float amax = 0.f;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int id = tid + 256 * s;
-        const int sr = id / 32, scol = 4 * (id % 32);
-        v[s] = T ? fetch4g(X, ldx, k0 + sr, r0 + scol, Kd, R, vec)
-                 : fetch4g(X, ldx, r0 + sr, k0 + scol, R, Kd, vec);
+    for (int s = 0; s < 16; ++s)
         amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v[s][0]), fabsf(v[s][1])),
                                  fmaxf(fabsf(v[s][2]), fabsf(v[s][3]))));
-    }
     amax = wave_max(amax);
     if ((tid & 63) == 0) wmax[tid >> 6] = amax;
     __syncthreads();

@@ -101,7 +101,7 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
     (void)K;
     if (path == MG_PATH_FP32) {
-        if (tiles(M, N, 256, 256) >= 256) return 1;
+        if (tiles(M, N, 256, 256) >= 256) return 5;
         if (tiles(M, N, 256, 128) >= 256) return 2;
         if (tiles(M, N, 128, 128) >= 128) return 0;
         return 3;

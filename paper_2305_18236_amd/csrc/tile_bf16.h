@@ -56,26 +56,6 @@ MG_DEVICE void round4(floatx4 x, uint32_t (&hi)[2])
     hi[1] = pack_bf16x2(x[2], x[3]);
 }
 
-// Guarded 16-byte fetch of four consecutive stored columns (gc .. gc+3) of
-// stored row gr; out-of-range elements read 0.
-MG_DEVICE floatx4 fetch4(const float* __restrict__ src, int64_t ld, int64_t gr, int64_t gc,
-                         int64_t R, int64_t Cn, bool vec)
-{
-    floatx4 x = {0.f, 0.f, 0.f, 0.f};
-    if (gr < R) {
-        const float* p = src + gr * ld + gc;
-        if (vec && gc + 3 < Cn) {
-            x = *reinterpret_cast<const floatx4*>(p);
-        } else {
-            if (gc + 0 < Cn) x[0] = p[0];
-            if (gc + 1 < Cn) x[1] = p[1];
-            if (gc + 2 < Cn) x[2] = p[2];
-            if (gc + 3 < Cn) x[3] = p[3];
-        }
-    }
-    return x;
-}
-
 // One operand panel: ROWS (m or n) x BK (k), FP32 in global memory, packed
 // into LDS as bf16 rows of LDR = BK + PAD elements.
 //   KSRC: the stored matrix is k-contiguous (A 'N', B 'T'); a chunk is four
@@ -96,23 +76,51 @@ struct BfPanel {
     MG_DEVICE void load(const float* __restrict__ src, int64_t ld, int64_t mn0, int64_t k0,
                         int64_t R, int64_t Cn, bool vec, int tid)
     {
-        if (KSRC) {
+        // stored-panel origin and extent: KSRC rows are mn, columns k; else rows k, columns mn
+        const int64_t r0 = KSRC ? mn0 : k0, c0 = KSRC ? k0 : mn0;
+        const int SR = KSRC ? ROWS : BK, SC = KSRC ? BK : ROWS;
+        // Wave-uniform test: interior panels take the branch-free path, so all
+        // their loads are in flight at once; edge panels take the guarded path.
+        if (vec && r0 + SR <= R && c0 + SC <= Cn) {
+            const float* __restrict__ base = src + r0 * ld + c0;
+            if (KSRC) {
 #pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const int q = tid + s * NT;
-                if (CHUNKS % NT != 0 && q >= CHUNKS) break;
-                const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
-                v[s] = fetch4(src, ld, mn0 + r, k0 + c, R, Cn, vec);
+                for (int s = 0; s < PER; ++s) {
+                    const int q = tid + s * NT;
+                    if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+                    const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                    v[s] = *reinterpret_cast<const floatx4*>(base + r * ld + c);
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < PER; ++b) {
+                    const int q = tid + b * NT;
+                    if (BLOCKS % NT != 0 && q >= BLOCKS) break;
+                    const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        v[4 * b + e] = *reinterpret_cast<const floatx4*>(base + (4 * kb + e) * ld + 4 * mb);
+                }
             }
         } else {
+            if (KSRC) {
 #pragma unroll
-            for (int b = 0; b < PER; ++b) {
-                const int q = tid + b * NT;
-                if (BLOCKS % NT != 0 && q >= BLOCKS) break;
-                const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+                for (int s = 0; s < PER; ++s) {
+                    const int q = tid + s * NT;
+                    if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+                    const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                    v[s] = fetch4_guarded(src, ld, mn0 + r, k0 + c, R, Cn, vec);
+                }
+            } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    v[4 * b + e] = fetch4(src, ld, k0 + 4 * kb + e, mn0 + 4 * mb, R, Cn, vec);
+                for (int b = 0; b < PER; ++b) {
+                    const int q = tid + b * NT;
+                    if (BLOCKS % NT != 0 && q >= BLOCKS) break;
+                    const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        v[4 * b + e] = fetch4_guarded(src, ld, k0 + 4 * kb + e, mn0 + 4 * mb, R, Cn, vec);
+                }
             }
         }
     }

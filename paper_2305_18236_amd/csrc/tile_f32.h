@@ -58,26 +58,24 @@ struct PanelLoader {
     MG_DEVICE void load(const float* __restrict__ src, int64_t ld, int64_t r0, int64_t c0,
                         int64_t R, int64_t Cn, bool vec, int tid)
     {
+        // Wave-uniform test: an interior panel with 16-byte access takes the
+        // branch-free path, so all its loads are in flight at once; edge
+        // panels take the guarded path.
+        if (vec && r0 + SR <= R && c0 + SC <= Cn) {
+            const float* __restrict__ base = src + r0 * ld + c0;
 #pragma unroll
-        for (int s = 0; s < PER_THREAD; ++s) {
-            const int q = tid + s * NT;
-            const int r = q / (SC / 4);
-            const int c = (q % (SC / 4)) * 4;
-            const int64_t gr = r0 + r;
-            const int64_t gc = c0 + c;
-            floatx4 x = {0.f, 0.f, 0.f, 0.f};
-            if (gr < R) {
-                const float* p = src + gr * ld + gc;
-                if (vec && gc + 3 < Cn) {
-                    x = *reinterpret_cast<const floatx4*>(p);
-                } else {
-                    if (gc + 0 < Cn) x[0] = p[0];
-                    if (gc + 1 < Cn) x[1] = p[1];
-                    if (gc + 2 < Cn) x[2] = p[2];
-                    if (gc + 3 < Cn) x[3] = p[3];
-                }
+            for (int s = 0; s < PER_THREAD; ++s) {
+                const int q = tid + s * NT;
+                const int r = q / (SC / 4), c = (q % (SC / 4)) * 4;
+                v[s] = *reinterpret_cast<const floatx4*>(base + r * ld + c);
             }
-            v[s] = x;
+        } else {
+#pragma unroll
+            for (int s = 0; s < PER_THREAD; ++s) {
+                const int q = tid + s * NT;
+                const int r = q / (SC / 4), c = (q % (SC / 4)) * 4;
+                v[s] = fetch4_guarded(src, ld, r0 + r, c0 + c, R, Cn, vec);
+            }
         }
     }
 
@@ -188,27 +186,46 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
     }
     __syncthreads();
 
+    constexpr int STEPS = BK / 2;          // MFMA k-steps per panel
+    constexpr int PACK_AT = STEPS / 2;     // the next panel is packed half-way
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) fetch(int64_t(kt + 1) * BK);
+        if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
 
         const float* a_base = As[cur] + wm0 + V * c;
         const float* b_base = Bs[cur] + wn0 + H * c;
+        // Software pipeline: the fragments of step s+1 are read from LDS
+        // before the MFMAs of step s are issued, into separate registers, so
+        // LDS latency hides behind the matrix core.
+        float a[V], b[H];
+        lds_read<V>(a_base + h * BM, a);
+        lds_read<H>(b_base + h * BN, b);
 #pragma unroll
-        for (int s = 0; s < BK / 2; ++s) {
-            const int k = 2 * s + h;
-            float a[V], b[H];
-            lds_read<V>(a_base + k * BM, a);
-            lds_read<H>(b_base + k * BN, b);
+        for (int s = 0; s < STEPS; ++s) {
+            float an[V], bn[H];
+            if (s + 1 < STEPS) {
+                const int k = 2 * (s + 1) + h;
+                lds_read<V>(a_base + k * BM, an);
+                lds_read<H>(b_base + k * BN, bn);
+            }
+            if (s == PACK_AT) {
+                // Pack the panel fetched at the top of this iteration into the
+                // other LDS buffer (last read before the previous barrier).
+                // On the last panel this rewrites stale data nobody reads.
+                pack(cur ^ 1);
+            }
 #pragma unroll
             for (int i = 0; i < V; ++i)
 #pragma unroll
                 for (int j = 0; j < H; ++j)
                     acc[i][j] = mfma_f32_32x32x2(a[i], b[j], acc[i][j]);
+            if (s + 1 < STEPS) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) a[i] = an[i];
+#pragma unroll
+                for (int j = 0; j < H; ++j) b[j] = bn[j];
+            }
         }
-
-        if (more) pack(cur ^ 1);
         __syncthreads();
     }
 

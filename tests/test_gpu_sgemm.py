@@ -55,7 +55,7 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     """Each tile configuration over several tiles and a ragged tail."""
@@ -113,6 +113,18 @@ def test_m_or_n_zero_touches_nothing(gpu):
     p = Problem(0, 5, 7, seed=12)
     p.to_device(gpu)
     assert p.run() == 0
+
+
+def test_layouts_bitwise_identical(gpu):
+    """Packing hands the micro-kernel the same panels for every stored layout,
+    so NN/NT/TN/TT of the same logical operands give identical bits."""
+    outs = []
+    for tA, tB in LAYOUTS:
+        p = Problem(333, 290, 300, tA, tB, 1.5, 0.5, seed=21).to_device(gpu)
+        assert p.run() == 0
+        outs.append(p.result())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
 
 
 def test_deterministic_bitwise(gpu):
