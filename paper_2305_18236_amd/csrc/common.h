@@ -25,7 +25,14 @@ struct GemmArgs {
     float alpha, beta;
     int tiles_m, tiles_n;
     int group_m;      // tile rows per raster group (L2 reuse of B panels)
-    int vec_a, vec_b, vec_c;   // 16-byte vector access allowed for A, B, C
+    // vec_a / vec_b: 16-byte loads allowed (16-byte aligned, ld % 4 == 0) and
+    // in-panel byte offsets fit 32 bits (ld < 2^22 - 64), which lets interior
+    // panels address through a uniform base plus a 32-bit per-lane offset.
+    // vec_c: 16-byte aligned C with ldc % 4 == 0.
+    int vec_a, vec_b, vec_c;
+    // Pre-packed BF16 operands only: element offset from the hi plane of
+    // op(A) (op(B)^T) to its lo plane.
+    int64_t plane_a, plane_b;
 };
 
 // Arguments of the FP8 GEMM on packed operands (see gemm_fp8.hip).
@@ -84,6 +91,18 @@ MG_DEVICE floatx4 fetch4_guarded(const float* __restrict__ src, int64_t ld, int6
         }
     }
     return x;
+}
+
+// 16-byte load at a uniform base plus a 32-bit per-lane BYTE offset: the
+// form the global_load ... saddr instructions take (one VGPR per address).
+MG_DEVICE floatx4 load16(const float* __restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const floatx4*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+MG_DEVICE uint4 load16u(const void* __restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
 MG_DEVICE floatx16 mfma_f32_32x32x2(float a, float b, floatx16 c)

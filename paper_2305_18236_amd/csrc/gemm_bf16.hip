@@ -15,14 +15,27 @@ void gemm_bf16_kernel(GemmArgs g)
     bf16_tile<BM, BN, BK, WM, WN, TA, TB, TERMS>(g, tm, tn, smem);
 }
 
+// GEMM on operands pre-packed by bf16_pack_kernel (no conversion, no bounds
+// checks on loads; the epilogue still clips to M x N).
 template <int BM, int BN, int BK, int WM, int WN, int TERMS>
-static hipError_t launch_bf16_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stream)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_bf16_packed_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<BM, BN, BK, TERMS>()];
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS, true>(g, tm, tn, smem);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int TERMS>
+static hipError_t launch_bf16_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stream, bool packed)
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
     const dim3 grid(g.tiles_m * g.tiles_n), block(NT);
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, false, false, TERMS>), grid, block, 0, stream, g);
+    if (packed) hipLaunchKernelGGL((gemm_bf16_packed_kernel<BM, BN, BK, WM, WN, TERMS>), grid, block, 0, stream, g);
+    else if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, false, false, TERMS>), grid, block, 0, stream, g);
     else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, false, true, TERMS>), grid, block, 0, stream, g);
     else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, true, false, TERMS>), grid, block, 0, stream, g);
     else hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, true, true, TERMS>), grid, block, 0, stream, g);
@@ -41,22 +54,106 @@ const SgemmConfig kBf16Configs[] = {
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
 template <int TERMS>
-static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream)
+static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream, bool packed)
 {
     switch (cfg) {
-    case 0: return launch_bf16_cfg<256, 256, 32, 128, 128, TERMS>(ta, tb, g, stream);
-    case 1: return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream);
-    case 2: return launch_bf16_cfg<128, 128, 32, 64, 64, TERMS>(ta, tb, g, stream);
-    case 3: return launch_bf16_cfg<256, 128, 32, 128, 64, TERMS>(ta, tb, g, stream);
-    case 4: return launch_bf16_cfg<64, 64, 32, 32, 32, TERMS>(ta, tb, g, stream);
-    case 5: return launch_bf16_cfg<128, 64, 32, 64, 32, TERMS>(ta, tb, g, stream);
+    case 0: return launch_bf16_cfg<256, 256, 32, 128, 128, TERMS>(ta, tb, g, stream, packed);
+    case 1: return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
+    case 2: return launch_bf16_cfg<128, 128, 32, 64, 64, TERMS>(ta, tb, g, stream, packed);
+    case 3: return launch_bf16_cfg<256, 128, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
+    case 4: return launch_bf16_cfg<64, 64, 32, 32, 32, TERMS>(ta, tb, g, stream, packed);
+    case 5: return launch_bf16_cfg<128, 64, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream)
+hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream, bool packed)
 {
-    return terms == 3 ? launch_terms<3>(cfg, ta, tb, g, stream) : launch_terms<1>(cfg, ta, tb, g, stream);
+    return terms == 3 ? launch_terms<3>(cfg, ta, tb, g, stream, packed)
+                      : launch_terms<1>(cfg, ta, tb, g, stream, packed);
+}
+
+// ---------------------------------------------------------------------------
+// Pre-pack of one operand for the BF16 paths: the logical R x Kd matrix
+// op(X) (stored R x Kd when T is false, Kd x R when true) is rounded (TERMS 1)
+// or split into hi/lo (TERMS 3) once and written as k-contiguous bf16 rows
+// hi[Rp][ldq] (and lo[Rp][ldq]), zero outside R x Kd.  One workgroup of 256
+// threads per 128 x 128 tile; the tile goes through LDS so that both stored
+// layouts write whole 16-byte row chunks.
+constexpr int PT = 128;          // pack tile
+constexpr int PROW = PT + 8;     // LDS row of the pack tile (bf16)
+
+template <bool T, int TERMS>
+__global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict__ X, int64_t ldx, int64_t R,
+                                                        int64_t Kd, int vec, uint16_t* __restrict__ hi,
+                                                        uint16_t* __restrict__ lo, int64_t ldq)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t th[PT * PROW];
+    __shared__ __attribute__((aligned(16))) uint16_t tl[TERMS == 3 ? PT * PROW : 8];
+    const int tid = threadIdx.x;
+    const int64_t k0 = int64_t(blockIdx.x) * PT, r0 = int64_t(blockIdx.y) * PT;
+    const int64_t sr0 = T ? k0 : r0, sc0 = T ? r0 : k0;      // stored tile origin
+    const int64_t SRn = T ? Kd : R, SCn = T ? R : Kd;         // stored valid extent
+    floatx4 v[16];
+    if (vec && sr0 + PT <= SRn && sc0 + PT <= SCn) {          // wave-uniform: interior tile
+        const float* __restrict__ base = X + sr0 * ldx + sc0;
+        const uint32_t ld32 = uint32_t(ldx);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const uint32_t id = tid + 256 * s;
+            v[s] = load16(base, ((id / 32) * ld32 + 4 * (id % 32)) * 4u);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int id = tid + 256 * s;
+            v[s] = fetch4_guarded(X, ldx, sr0 + id / 32, sc0 + 4 * (id % 32), SRn, SCn, vec);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int id = tid + 256 * s;
+        const int sr = id / 32, scol = 4 * (id % 32);
+        uint32_t h[2], l[2];
+        if (TERMS == 3) split4(v[s], h, l);
+        else round4(v[s], h);
+        if (!T) {
+            // stored row = logical row, columns = k .. k+3
+            *reinterpret_cast<uint2*>(&th[sr * PROW + scol]) = make_uint2(h[0], h[1]);
+            if (TERMS == 3) *reinterpret_cast<uint2*>(&tl[sr * PROW + scol]) = make_uint2(l[0], l[1]);
+        } else {
+            // stored row = k, columns = four consecutive logical rows
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                th[(scol + b) * PROW + sr] = uint16_t(h[b >> 1] >> (16 * (b & 1)));
+                if (TERMS == 3) tl[(scol + b) * PROW + sr] = uint16_t(l[b >> 1] >> (16 * (b & 1)));
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int id = tid + 256 * s;
+        const int r = id / 16, c = 8 * (id % 16);
+        *reinterpret_cast<uint4*>(hi + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&th[r * PROW + c]);
+        if (TERMS == 3)
+            *reinterpret_cast<uint4*>(lo + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tl[r * PROW + c]);
+    }
+}
+
+hipError_t launch_bf16_pack(bool trans, int terms, const float* X, int64_t ldx, int64_t R, int64_t Kd,
+                            bool vec, uint16_t* hi, uint16_t* lo, int64_t ldq, int64_t Rp, int64_t Kp,
+                            hipStream_t stream)
+{
+    const dim3 grid(unsigned(Kp / PT), unsigned(Rp / PT)), block(256);
+    if (terms == 3) {
+        if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 3>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+        else hipLaunchKernelGGL((bf16_pack_kernel<false, 3>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+    } else {
+        if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 1>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+        else hipLaunchKernelGGL((bf16_pack_kernel<false, 1>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -49,6 +49,9 @@ int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, const fl
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// 16-byte panel loads with 32-bit in-panel offsets (see GemmArgs::vec_a).
+bool fast_operand(const void* p, int64_t ld) { return aligned16(p) && ld % 4 == 0 && ld < (int64_t(1) << 22) - 64; }
+
 int64_t tiles(int64_t M, int64_t N, int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); }
 
 struct ConfigTable {
@@ -111,6 +114,7 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         if (tiles(M, N, 128, 128) >= 128) return 2;
         return 3;
     }
+    if (path == MG_PATH_BF16 && tiles(M, N, 128, 128) >= 1024) return 2;   // pre-packed: 128 x 128 best
     if (tiles(M, N, 256, 256) >= 256) return 1;
     if (tiles(M, N, 256, 128) >= 256) return 3;
     if (tiles(M, N, 128, 128) >= 128) return 2;
@@ -139,6 +143,40 @@ Fp8Workspace fp8_workspace(int64_t M, int64_t N, int64_t K)
     w.sa = w.qb + align256(fp8_q_bytes(N, K));
     w.sb = w.sa + align256(fp8_s_bytes(M, K));
     w.total = w.sb + align256(fp8_s_bytes(N, K));
+    return w;
+}
+
+// ---- BF16 paths, pre-packed form: hi (and lo) planes of op(A) and op(B)^T,
+// rows padded to 256, K padded to 128, bf16.  Used where converting each
+// operand once beats converting it in every workgroup that reads it, as
+// measured at 8192^3 on MI355X: plain BF16 (687 vs 482 TFLOP/s: the packed
+// operands also halve the GEMM's global traffic) for min(M, N) >= 512.  On
+// bf16x3 the packed operands are as large as the FP32 ones and the in-kernel
+// conversion hides behind the matrix core (about 370 vs 347 TFLOP/s), so
+// bf16x3 converts in the kernel.
+bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
+{
+    return path == MG_PATH_BF16 && M >= 512 && N >= 512 && K >= 32;
+}
+
+struct Bf16Workspace {
+    int64_t Mp, Np, Kp;
+    size_t a_hi, a_lo, b_hi, b_lo, total;
+};
+
+Bf16Workspace bf16_workspace(int path, int64_t M, int64_t N, int64_t K)
+{
+    Bf16Workspace w{};
+    const int nl = path == MG_PATH_BF16X3 ? 2 : 1;
+    w.Mp = round_up(M, 256);
+    w.Np = round_up(N, 256);
+    w.Kp = round_up(K, 128);
+    const size_t pa = align256(size_t(w.Mp) * size_t(w.Kp) * 2), pb = align256(size_t(w.Np) * size_t(w.Kp) * 2);
+    w.a_hi = 0;
+    w.a_lo = pa;                       // used only when nl == 2
+    w.b_hi = size_t(nl) * pa;
+    w.b_lo = w.b_hi + pb;
+    w.total = size_t(nl) * (pa + pb);
     return w;
 }
 
@@ -176,7 +214,7 @@ int pick_config(int path, int64_t M, int64_t N, int64_t K)
 
 int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
              const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
-             int64_t ldc, hipStream_t stream)
+             int64_t ldc, hipStream_t stream, void* bf16_planes = nullptr)
 {
     const int cfg = pick_config(path, M, N, K);
     const ConfigTable t = table_of(path);
@@ -188,13 +226,36 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.alpha = alpha; g.beta = beta;
     g.group_m = 4;
-    g.vec_a = aligned16(A) && lda % 4 == 0;
-    g.vec_b = aligned16(B) && ldb % 4 == 0;
+    g.vec_a = fast_operand(A, lda);
+    g.vec_b = fast_operand(B, ldb);
     g.vec_c = aligned16(C) && ldc % 4 == 0;
     switch (path) {
     case MG_PATH_FP32: return hip_status(mg::launch_sgemm(cfg, ta, tb, g, stream));
-    case MG_PATH_BF16X3: return hip_status(mg::launch_gemm_bf16(3, cfg, ta, tb, g, stream));
-    case MG_PATH_BF16: return hip_status(mg::launch_gemm_bf16(1, cfg, ta, tb, g, stream));
+    case MG_PATH_BF16X3:
+    case MG_PATH_BF16: {
+        const int terms = path == MG_PATH_BF16X3 ? 3 : 1;
+        if (bf16_planes == nullptr) return hip_status(mg::launch_gemm_bf16(terms, cfg, ta, tb, g, stream));
+        // pack each operand once, then multiply the packed planes
+        const Bf16Workspace w = bf16_workspace(path, M, N, K);
+        uint8_t* base = static_cast<uint8_t*>(bf16_planes);
+        uint16_t* ahi = reinterpret_cast<uint16_t*>(base + w.a_hi);
+        uint16_t* alo = reinterpret_cast<uint16_t*>(base + w.a_lo);
+        uint16_t* bhi = reinterpret_cast<uint16_t*>(base + w.b_hi);
+        uint16_t* blo = reinterpret_cast<uint16_t*>(base + w.b_lo);
+        hipError_t e = mg::launch_bf16_pack(ta, terms, A, lda, M, K, fast_operand(A, lda), ahi, alo, w.Kp,
+                                            w.Mp, w.Kp, stream);
+        if (e != hipSuccess) return hip_status(e);
+        // op(B)^T is N x K: stored as is when transB is 'T', transposed when 'N'
+        e = mg::launch_bf16_pack(!tb, terms, B, ldb, N, K, fast_operand(B, ldb), bhi, blo, w.Kp, w.Np, w.Kp,
+                                 stream);
+        if (e != hipSuccess) return hip_status(e);
+        g.A = reinterpret_cast<const float*>(ahi);
+        g.B = reinterpret_cast<const float*>(bhi);
+        g.lda = g.ldb = w.Kp;
+        g.plane_a = int64_t(w.a_lo - w.a_hi) / 2;
+        g.plane_b = int64_t(w.b_lo - w.b_hi) / 2;
+        return hip_status(mg::launch_gemm_bf16(terms, cfg, false, true, g, stream, true));
+    }
     default: return MG_ERR_UNSUPPORTED;
     }
 }
@@ -277,7 +338,11 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
         return run_fp8_packed(M, N, K, alpha, base + w.qa, base + w.sa, base + w.qb, base + w.sb,
                               beta, C, ldc, s);
     }
-    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    void* planes = nullptr;
+    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K) && workspace != nullptr &&
+        workspace_bytes >= bf16_workspace(path, M, N, K).total && (reinterpret_cast<uintptr_t>(workspace) & 255) == 0)
+        planes = workspace;
+    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, planes);
 }
 
 int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
@@ -291,8 +356,11 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
 {
     (void)transA; (void)transB;
-    if (path != MG_PATH_FP8_T128 || M <= 0 || N <= 0 || K <= 0) return 0;
-    return fp8_workspace(M, N, K).total;
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
+    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K))
+        return bf16_workspace(path, M, N, K).total;
+    return 0;
 }
 
 int mg_fp8_packed_size(int64_t R, int64_t K, size_t* q_bytes, size_t* scale_bytes)
@@ -468,8 +536,8 @@ int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* w
         b.g.tiles_m = int((q.M + c.bm - 1) / c.bm);
         b.g.tiles_n = int((q.N + c.bn - 1) / c.bn);
         b.g.group_m = 1;
-        b.g.vec_a = aligned16(q.A) && q.lda % 4 == 0;
-        b.g.vec_b = aligned16(q.B) && q.ldb % 4 == 0;
+        b.g.vec_a = fast_operand(q.A, q.lda);
+        b.g.vec_b = fast_operand(q.B, q.ldb);
         b.g.vec_c = aligned16(q.C) && q.ldc % 4 == 0;
         host.push_back(b);
     }

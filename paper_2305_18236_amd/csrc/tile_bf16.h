@@ -63,8 +63,20 @@ MG_DEVICE void round4(floatx4 x, uint32_t (&hi)[2])
 //   else: the stored matrix is mn-contiguous (A 'T', B 'N'); a block is four
 //         k rows x four mn columns, fetched as four 16-byte loads and
 //         transposed in registers into four 8-byte LDS writes per term.
+// Lane order of the pack (LDS rows are LDR = BK + 8 bf16 = 80 bytes for
+// BK = 32; 64 banks of 4 bytes):
+//   KSRC: eight lanes cover one row's BK values (one 128-byte global line);
+//         the row of lane group rr is row_perm(rr), which puts rows
+//         0, 4, 8, 12 in one 32-lane write so their 64-byte pieces start at
+//         bank offsets 0, 16, 32, 48 (row stride 20 dwords) and never collide;
+//   else: lanes run over the BK/4 k-blocks first, then over mn-blocks, so one
+//         8-byte write instruction stores 8 k-blocks of 4 rows spaced 4 apart:
+//         dword 80*mb + 2*kb mod 64 is distinct for every lane.
+MG_DEVICE int row_perm(int rr) { return (rr & ~15) | ((rr & 3) << 2) | ((rr >> 2) & 3); }
+
 template <int ROWS, int BK, int LDR, int NT, bool KSRC, int TERMS>
 struct BfPanel {
+    static_assert(ROWS % 16 == 0, "row permutation works on groups of 16 rows");
     static constexpr int CHUNKS = ROWS * BK / 4;    // 16-byte chunks (KSRC)
     static constexpr int BLOCKS = ROWS * BK / 16;   // 4x4 blocks (mn-contiguous source)
     static constexpr int PER = KSRC ? (CHUNKS + NT - 1) / NT : (BLOCKS + NT - 1) / NT;
@@ -82,24 +94,26 @@ struct BfPanel {
         // Wave-uniform test: interior panels take the branch-free path, so all
         // their loads are in flight at once; edge panels take the guarded path.
         if (vec && r0 + SR <= R && c0 + SC <= Cn) {
+            // uniform base + 32-bit per-lane offset (vec guarantees it fits)
             const float* __restrict__ base = src + r0 * ld + c0;
+            const uint32_t ld32 = uint32_t(ld);
             if (KSRC) {
 #pragma unroll
                 for (int s = 0; s < PER; ++s) {
                     const int q = tid + s * NT;
                     if (CHUNKS % NT != 0 && q >= CHUNKS) break;
-                    const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
-                    v[s] = *reinterpret_cast<const floatx4*>(base + r * ld + c);
+                    const uint32_t r = row_perm(q / (BK / 4)), c = (q % (BK / 4)) * 4;
+                    v[s] = load16(base, (r * ld32 + c) * 4u);
                 }
             } else {
 #pragma unroll
                 for (int b = 0; b < PER; ++b) {
                     const int q = tid + b * NT;
                     if (BLOCKS % NT != 0 && q >= BLOCKS) break;
-                    const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+                    const uint32_t kb = q % (BK / 4), mb = q / (BK / 4);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        v[4 * b + e] = *reinterpret_cast<const floatx4*>(base + (4 * kb + e) * ld + 4 * mb);
+                        v[4 * b + e] = load16(base, ((4 * kb + e) * ld32 + 4 * mb) * 4u);
                 }
             }
         } else {
@@ -108,7 +122,7 @@ struct BfPanel {
                 for (int s = 0; s < PER; ++s) {
                     const int q = tid + s * NT;
                     if (CHUNKS % NT != 0 && q >= CHUNKS) break;
-                    const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                    const int r = row_perm(q / (BK / 4)), c = (q % (BK / 4)) * 4;
                     v[s] = fetch4_guarded(src, ld, mn0 + r, k0 + c, R, Cn, vec);
                 }
             } else {
@@ -116,7 +130,7 @@ struct BfPanel {
                 for (int b = 0; b < PER; ++b) {
                     const int q = tid + b * NT;
                     if (BLOCKS % NT != 0 && q >= BLOCKS) break;
-                    const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+                    const int kb = q % (BK / 4), mb = q / (BK / 4);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         v[4 * b + e] = fetch4_guarded(src, ld, k0 + 4 * kb + e, mn0 + 4 * mb, R, Cn, vec);
@@ -132,7 +146,7 @@ struct BfPanel {
             for (int s = 0; s < PER; ++s) {
                 const int q = tid + s * NT;
                 if (CHUNKS % NT != 0 && q >= CHUNKS) break;
-                const int r = q / (BK / 4), c = (q % (BK / 4)) * 4;
+                const int r = row_perm(q / (BK / 4)), c = (q % (BK / 4)) * 4;
                 put(hi_lds, lo_lds, r * LDR + c, v[s]);
             }
         } else {
@@ -140,7 +154,7 @@ struct BfPanel {
             for (int b = 0; b < PER; ++b) {
                 const int q = tid + b * NT;
                 if (BLOCKS % NT != 0 && q >= BLOCKS) break;
-                const int kb = q / (ROWS / 4), mb = q % (ROWS / 4);
+                const int kb = q % (BK / 4), mb = q / (BK / 4);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const floatx4 col = {v[4 * b + 0][t], v[4 * b + 1][t], v[4 * b + 2][t], v[4 * b + 3][t]};
@@ -171,7 +185,62 @@ constexpr int bf16_lds_elems() { return 2 * (TERMS == 3 ? 2 : 1) * (BM + BN) * (
 // One BM x BN output tile (tm, tn), computed by the whole workgroup.  smem:
 // bf16_lds_elems() 16-bit elements of LDS, 16-byte aligned.  Ends with a
 // workgroup barrier after the last LDS read.
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int TERMS>
+// One operand panel read from PRE-PACKED bf16 planes (bf16_pack_kernel): rows
+// of ld bf16 (k-contiguous, zero-padded), hi plane at `hi`, lo plane at
+// hi + plane.  The pack to LDS is a plain 16-byte copy; lanes take four
+// 16-byte chunks of one row, rows in row_perm order, so a 16-lane write
+// covers rows 0, 4, 8, 12 at bank offsets 0, 16, 32, 48 (conflict-free).
+template <int ROWS, int BK, int LDR, int NT, int TERMS>
+struct BfPackedPanel {
+    static constexpr int CPR = BK / 8;          // 16-byte chunks per row and plane
+    static constexpr int CHUNKS = ROWS * CPR;
+    static constexpr int PER = (CHUNKS + NT - 1) / NT;
+    static constexpr int NL = (TERMS == 3) ? 2 : 1;
+    static_assert(ROWS % 16 == 0, "row permutation works on groups of 16 rows");
+    uint4 v[NL][PER];
+
+    MG_DEVICE void load(const uint16_t* __restrict__ hi, int64_t plane, int64_t ld, int64_t mn0,
+                        int64_t k0, int tid)
+    {
+        const uint16_t* __restrict__ base = hi + mn0 * ld + k0;
+        const uint32_t ld32 = uint32_t(ld);
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const int q = tid + s * NT;
+            if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+            const uint32_t r = row_perm(q / CPR), c = (q % CPR) * 8;
+            const uint32_t off = (r * ld32 + c) * 2u;
+            v[0][s] = load16u(base, off);
+            if (TERMS == 3) v[NL - 1][s] = load16u(base + plane, off);
+        }
+    }
+
+    MG_DEVICE void store(uint16_t* hi_lds, uint16_t* lo_lds, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const int q = tid + s * NT;
+            if (CHUNKS % NT != 0 && q >= CHUNKS) break;
+            const int r = row_perm(q / CPR), c = (q % CPR) * 8;
+            *reinterpret_cast<uint4*>(hi_lds + r * LDR + c) = v[0][s];
+            if (TERMS == 3) *reinterpret_cast<uint4*>(lo_lds + r * LDR + c) = v[NL - 1][s];
+        }
+    }
+};
+
+template <bool PACKED, int ROWS, int BK, int LDR, int NT, bool KSRC, int TERMS>
+struct BfLoaderSel {
+    using type = BfPanel<ROWS, BK, LDR, NT, KSRC, TERMS>;
+};
+template <int ROWS, int BK, int LDR, int NT, bool KSRC, int TERMS>
+struct BfLoaderSel<true, ROWS, BK, LDR, NT, KSRC, TERMS> {
+    using type = BfPackedPanel<ROWS, BK, LDR, NT, TERMS>;
+};
+
+// PACKED: g.A / g.B point at the hi planes of pre-packed op(A) / op(B)^T
+// (bf16, row stride lda / ldb, zero-padded to whole tiles and panels), TA/TB
+// are ignored and no bounds checks are needed on the loads.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int TERMS, bool PACKED = false>
 MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
 {
     constexpr int WAVES_N = BN / WN;
@@ -192,15 +261,21 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
 
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
-    BfPanel<BM, BK, LDR, NT, !TA, TERMS> pa;
-    BfPanel<BN, BK, LDR, NT, TB, TERMS> pb;
+    typename BfLoaderSel<PACKED, BM, BK, LDR, NT, !TA, TERMS>::type pa;
+    typename BfLoaderSel<PACKED, BN, BK, LDR, NT, TB, TERMS>::type pb;
     // Stored extents: A is M x K ('N') or K x M ('T'); B is K x N ('N') or N x K ('T').
     const int64_t Ra = TA ? g.K : g.M, Ca = TA ? g.M : g.K;
     const int64_t Rb = TB ? g.N : g.K, Cb = TB ? g.K : g.N;
+    (void)Ra; (void)Ca; (void)Rb; (void)Cb;
 
     auto fetch = [&](int64_t k0) {
-        pa.load(g.A, g.lda, m0, k0, Ra, Ca, g.vec_a, tid);
-        pb.load(g.B, g.ldb, n0, k0, Rb, Cb, g.vec_b, tid);
+        if constexpr (PACKED) {
+            pa.load(reinterpret_cast<const uint16_t*>(g.A), g.plane_a, g.lda, m0, k0, tid);
+            pb.load(reinterpret_cast<const uint16_t*>(g.B), g.plane_b, g.ldb, n0, k0, tid);
+        } else {
+            pa.load(g.A, g.lda, m0, k0, Ra, Ca, g.vec_a, tid);
+            pb.load(g.B, g.ldb, n0, k0, Rb, Cb, g.vec_b, tid);
+        }
     };
     auto pack = [&](int buf) {
         pa.store(As[buf][0], As[buf][NL - 1], tid);
@@ -222,13 +297,17 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
     }
     __syncthreads();
 
+    constexpr int STEPS = BK / 16;          // MFMA k-steps per panel
+    // Where the next panel is converted and packed: after the last MFMA step
+    // (PACK_AT == STEPS).  Packing half-way through the panel was measured
+    // slower here: the conversion's registers then overlap the fragments'.
+    constexpr int PACK_AT = STEPS;
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) fetch(int64_t(kt + 1) * BK);
+        if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
 
 #pragma unroll
-        for (int s = 0; s < BK / 16; ++s) {
+        for (int s = 0; s < STEPS; ++s) {
             const int koff = 16 * s + 8 * h;
             bf16x8 ah[V], bh[H], al[V], bl[H];
 #pragma unroll
@@ -242,6 +321,14 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
                 const int off = (wn0 + 32 * j + c) * LDR + koff;
                 bh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
                 if (TERMS == 3) bl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
+            }
+            if (s == PACK_AT) {
+                // Convert and pack the panel fetched at the top of this
+                // iteration into the other LDS buffer (last read before the
+                // previous barrier), between two MFMA groups so that its
+                // VALU work can run beside the matrix core.  On the last
+                // panel this rewrites stale data nobody reads.
+                pack(cur ^ 1);
             }
             if (TERMS == 3) {
                 // small terms first; consecutive instructions use different accumulators
@@ -262,8 +349,7 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
                 for (int j = 0; j < H; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
-
-        if (more) pack(cur ^ 1);
+        if (PACK_AT == STEPS) pack(cur ^ 1);   // the last panel rewrites stale data nobody reads
         __syncthreads();
     }
 

@@ -62,12 +62,14 @@ struct PanelLoader {
         // branch-free path, so all its loads are in flight at once; edge
         // panels take the guarded path.
         if (vec && r0 + SR <= R && c0 + SC <= Cn) {
+            // uniform base + 32-bit per-lane offset (vec guarantees it fits)
             const float* __restrict__ base = src + r0 * ld + c0;
+            const uint32_t ld32 = uint32_t(ld);
 #pragma unroll
             for (int s = 0; s < PER_THREAD; ++s) {
                 const int q = tid + s * NT;
-                const int r = q / (SC / 4), c = (q % (SC / 4)) * 4;
-                v[s] = *reinterpret_cast<const floatx4*>(base + r * ld + c);
+                const uint32_t r = q / (SC / 4), c = (q % (SC / 4)) * 4;
+                v[s] = load16(base, (r * ld32 + c) * 4u);
             }
         } else {
 #pragma unroll

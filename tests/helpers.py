@@ -87,12 +87,17 @@ class Problem:
         import torch
         self.dC.copy_(torch.from_numpy(self.Cbuf))
 
-    def run(self, path="fp32", workspace=None, stream=None):
-        """Call mg_gemm through the C ABI; returns the status code."""
+    def run(self, path="fp32", workspace=None, stream=None, use_workspace=True):
+        """Call mg_gemm through the C ABI; returns the status code.
+
+        use_workspace=False passes no workspace (the BF16 paths then convert
+        inside the GEMM instead of pre-packing)."""
         import torch
         from paper_2305_18236_amd import _native
         pid = PATH_ID[path]
         need = _native.mg_gemm_workspace_size(pid, self.tA, self.tB, self.M, self.N, self.K)
+        if not use_workspace:
+            need = 0
         ws_ptr, ws_bytes = None, 0
         if need:
             if workspace is None or workspace.numel() < need:

@@ -71,14 +71,14 @@ def _emulated_reference(p, terms):
     return C + C1 + C2
 
 
-def _check(p, dev, path, cfg=None):
+def _check(p, dev, path, cfg=None, use_workspace=True):
     nat = _native()
     pid = {"bf16x3": 1, "bf16": 2}[path]
     if cfg is not None:
         assert nat.mg_force_config(pid, cfg) == 0
     try:
         p.to_device(dev)
-        st = p.run(path)
+        st = p.run(path, use_workspace=use_workspace)
         assert st == 0, nat.status_string(st)
         C = p.result()
     finally:
@@ -105,10 +105,36 @@ def test_ragged_shapes_all_layouts(gpu, path, tA, tB, M, N, K):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, path, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, path, cfg=cfg)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+@pytest.mark.parametrize("use_workspace", [True, False])
+def test_prepacked_and_in_kernel_conversion(gpu, path, tA, tB, use_workspace):
+    """Large enough for the pre-packed form (operands converted once into
+    bf16 planes in the workspace), ragged in every dimension; without a
+    workspace the same problem converts inside the GEMM."""
+    _check(Problem(600, 530, 300, tA, tB, 1.5, 0.5, seed=ord(tA) + 3 * ord(tB)), gpu, path,
+           use_workspace=use_workspace)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+def test_prepacked_every_config(gpu, path, cfg):
+    _check(Problem(777, 531, 203, "T", "N", -1.0, 0.25, seed=100 + cfg), gpu, path, cfg=cfg)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "bf16"])
+def test_prepacked_integer_bit_exact_and_layout_invariant(gpu, path):
+    outs = []
+    for tA, tB in LAYOUTS:
+        C, Cref, _ = _check(Problem(520, 610, 250, tA, tB, 1.5, 0.5, seed=5, dist="integers"), gpu, path)
+        assert np.array_equal(C, Cref)
+        outs.append(C)
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
