@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain"], default="sgemm",
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8"], default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
                          "chain: forward + backward of Y = (X W1) W2")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -164,6 +164,8 @@ def main():
         return bench_batched(args, torch, si, native, dev)
     if args.workload == "chain":
         return bench_chain(args, torch, si, native, dev)
+    if args.workload == "fp8":
+        return bench_fp8(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -338,6 +340,73 @@ def bench_chain(args, torch, si, native, dev):
     out["ms_per_step"] = b["ms_per_step"]
     out["dtype"] = "bf16x3"
     out["speedup_bf16x3_vs_fp32"] = round(f["ms_per_step"] / b["ms_per_step"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def _time_ms(fn, steps, warmup, torch, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_fp8(args, torch, si, native, dev):
+    """The FP8 path at 8192^3 (NN, alpha 1, beta 0, U[-1, 1]): the two pack
+    (quantise) launches, the GEMM on packed operands alone, and the whole
+    mg_gemm call; plus the plain BF16 path for reference."""
+    A = torch.from_numpy(si.uniform((M, K), si.seed_for(3, "A"))).to(dev)
+    B = torch.from_numpy(si.uniform((K, N), si.seed_for(3, "B"))).to(dev)
+    C = torch.zeros((M, N), device=dev)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    qa_b, sa_b = native.mg_fp8_packed_size(M, K)
+    qb_b, sb_b = native.mg_fp8_packed_size(N, K)
+    qA = torch.empty(qa_b, dtype=torch.uint8, device=dev)
+    sA = torch.empty(sa_b, dtype=torch.uint8, device=dev)
+    qB = torch.empty(qb_b, dtype=torch.uint8, device=dev)
+    sB = torch.empty(sb_b, dtype=torch.uint8, device=dev)
+    need = native.mg_gemm_workspace_size(3, "N", "N", M, N, K)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def pack():
+        native.check(native.mg_fp8_pack("N", M, K, A.data_ptr(), K, qA.data_ptr(), sA.data_ptr(), sp), "pack A")
+        native.check(native.mg_fp8_pack("T", N, K, B.data_ptr(), N, qB.data_ptr(), sB.data_ptr(), sp), "pack B")
+
+    def gemm_only():
+        native.check(native.mg_gemm_fp8_packed(M, N, K, 1.0, qA.data_ptr(), sA.data_ptr(), qB.data_ptr(),
+                                               sB.data_ptr(), 0.0, C.data_ptr(), N, sp), "fp8 gemm")
+
+    def whole(path):
+        w = ws if path == 3 else torch.empty(max(native.mg_gemm_workspace_size(path, "N", "N", M, N, K), 1),
+                                             dtype=torch.uint8, device=dev)
+        n = native.mg_gemm_workspace_size(path, "N", "N", M, N, K)
+        return lambda: native.check(native.mg_gemm(path, "N", "N", M, N, K, 1.0, A.data_ptr(), K, B.data_ptr(), N,
+                                                   0.0, C.data_ptr(), N, w.data_ptr(), n, sp), "mg_gemm")
+
+    pack()
+    flops = 2.0 * M * N * K
+    t_pack = _time_ms(pack, args.steps, args.warmup, torch, stream)
+    t_gemm = _time_ms(gemm_only, args.steps, args.warmup, torch, stream)
+    t_whole = _time_ms(whole(3), args.steps, args.warmup, torch, stream)
+    t_bf16 = _time_ms(whole(2), args.steps, args.warmup, torch, stream)
+    pack_bytes = 2 * (4.0 + 1.0) * M * K        # read FP32, write E4M3, both operands
+    out = {"metric": "FP8 (E4M3, per-128x128-tile scales) GEMM TFLOP/s at 8192^3", "unit": "TFLOP/s",
+           "value": round(flops / (t_whole * 1e-3) / 1e12, 2), "ms_per_step": round(t_whole, 4),
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp8_e4m3", "data": "synthetic",
+           "config": {"workload": "gemm_fp8_t128_8192x8192x8192_nn", "M": M, "N": N, "K": K, "layout": "NN"},
+           "pack_ms": round(t_pack, 4), "pack_gbps": round(pack_bytes / (t_pack * 1e-3) / 1e9, 1),
+           "gemm_only_ms": round(t_gemm, 4),
+           "gemm_only_tflops": round(flops / (t_gemm * 1e-3) / 1e12, 2),
+           "gemm_only_pct_fp8_peak": round(100 * flops / (t_gemm * 1e-3) / 1e12 / PEAK_TFLOPS["fp8"], 2),
+           "bf16_tflops": round(flops / (t_bf16 * 1e-3) / 1e12, 2)}
     print(json.dumps(out), flush=True)
 
 

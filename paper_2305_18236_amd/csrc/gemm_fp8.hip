@@ -141,6 +141,36 @@ hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, i
 }
 
 // ---------------------------------------------------------------------------
+// One packed FP8 operand panel (ROWS rows of BK = 128 codes), staged through
+// registers into LDS rows of LDR bytes.  Eight lanes copy one 128-byte row.
+template <int ROWS, int NT, int LDR>
+struct Fp8Panel {
+    static constexpr int CHUNKS = ROWS * 128 / 16;
+    static constexpr int PER = CHUNKS / NT;
+    static_assert(CHUNKS % NT == 0, "panels must split evenly");
+    uint4 v[PER];
+
+    MG_DEVICE void load(const uint8_t* __restrict__ q, int64_t ldq, int64_t row0, int64_t k0, int tid)
+    {
+        const uint8_t* __restrict__ base = q + row0 * ldq + k0;
+        const uint32_t ld32 = uint32_t(ldq);
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const uint32_t id = tid + s * NT;
+            v[s] = load16u(base, (id / 8) * ld32 + 16 * (id % 8));
+        }
+    }
+
+    MG_DEVICE void store(uint8_t* lds, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const int id = tid + s * NT;
+            *reinterpret_cast<uint4*>(&lds[(id / 8) * LDR + 16 * (id % 8)]) = v[s];
+        }
+    }
+};
+
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void gemm_fp8_kernel(Fp8Args g)
@@ -150,8 +180,6 @@ void gemm_fp8_kernel(Fp8Args g)
     constexpr int WAVES_N = BN / WN;
     constexpr int NT = (BM / WM) * WAVES_N * 64;
     constexpr int V = WM / 32, H = WN / 32;
-    constexpr int CA = BM * BK / 16, CB = BN * BK / 16;   // 16-byte chunks per panel
-    static_assert(CA % NT == 0 && CB % NT == 0, "panels must split evenly");
 
     __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * LDR];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LDR];
@@ -165,31 +193,8 @@ void gemm_fp8_kernel(Fp8Args g)
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
-    uint4 ra[CA / NT], rb[CB / NT];
-    auto fetch = [&](int64_t k0) {
-#pragma unroll
-        for (int s = 0; s < CA / NT; ++s) {
-            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
-            ra[s] = *reinterpret_cast<const uint4*>(g.qA + (m0 + r) * g.ldq + k0 + cc);
-        }
-#pragma unroll
-        for (int s = 0; s < CB / NT; ++s) {
-            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
-            rb[s] = *reinterpret_cast<const uint4*>(g.qB + (n0 + r) * g.ldq + k0 + cc);
-        }
-    };
-    auto pack = [&](int buf) {
-#pragma unroll
-        for (int s = 0; s < CA / NT; ++s) {
-            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
-            *reinterpret_cast<uint4*>(&As[buf][r * LDR + cc]) = ra[s];
-        }
-#pragma unroll
-        for (int s = 0; s < CB / NT; ++s) {
-            const int id = tid + s * NT, r = id / 8, cc = 16 * (id % 8);
-            *reinterpret_cast<uint4*>(&Bs[buf][r * LDR + cc]) = rb[s];
-        }
-    };
+    Fp8Panel<BM, NT, LDR> pa;
+    Fp8Panel<BN, NT, LDR> pb;
 
     floatx16 acc[V][H];
 #pragma unroll
@@ -200,21 +205,41 @@ void gemm_fp8_kernel(Fp8Args g)
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int nk = int(g.Kp / BK);
-    fetch(0);
-    pack(0);
+    // Scale rows of this wave's MFMA blocks (wave-uniform).
+    int srow_a[V], srow_b[H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+        srow_a[i] = __builtin_amdgcn_readfirstlane(int((m0 + wm0 + 32 * i) / 128 * g.lds));
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+        srow_b[j] = __builtin_amdgcn_readfirstlane(int((n0 + wn0 + 32 * j) / 128 * g.lds));
+
+    // E8M0 scale bytes of the current panel (sa, sb) and of the next (sa_n, sb_n)
+    int sa[V], sb[H], sa_n[V], sb_n[H];
+#pragma unroll
+    for (int i = 0; i < V; ++i) sa[i] = g.sA[srow_a[i]];
+#pragma unroll
+    for (int j = 0; j < H; ++j) sb[j] = g.sB[srow_b[j]];
+    pa.load(g.qA, g.ldq, m0, 0, tid);
+    pb.load(g.qB, g.ldq, n0, 0, tid);
+    pa.store(As[0], tid);
+    pb.store(Bs[0], tid);
     __syncthreads();
 
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) fetch(int64_t(kt + 1) * BK);
-
-        // wave-uniform E8M0 scale bytes of this K-panel for each MFMA block
-        int sa[V], sb[H];
+        // Everything in one basic block, with the fetch of the next panel and
+        // its scale bytes issued before the MFMAs: the last panel re-fetches
+        // itself (inside the packed operands) and packs into the buffer nobody
+        // reads any more.
+        const int kn = kt + 1 < nk ? kt + 1 : kt;
+        pa.load(g.qA, g.ldq, m0, int64_t(kn) * BK, tid);
+        pb.load(g.qB, g.ldq, n0, int64_t(kn) * BK, tid);
 #pragma unroll
-        for (int i = 0; i < V; ++i) sa[i] = g.sA[((m0 + wm0 + 32 * i) / 128) * g.lds + kt];
+        for (int i = 0; i < V; ++i) sa_n[i] = g.sA[srow_a[i] + kn];
 #pragma unroll
-        for (int j = 0; j < H; ++j) sb[j] = g.sB[((n0 + wn0 + 32 * j) / 128) * g.lds + kt];
+        for (int j = 0; j < H; ++j) sb_n[j] = g.sB[srow_b[j] + kn];
+        __builtin_amdgcn_sched_barrier(0);
 
 #pragma unroll
         for (int s = 0; s < BK / 64; ++s) {
@@ -242,7 +267,14 @@ void gemm_fp8_kernel(Fp8Args g)
                         a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
         }
 
-        if (more) pack(cur ^ 1);
+        // keep the pack, which waits for the loads above, after the MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        pa.store(As[cur ^ 1], tid);
+        pb.store(Bs[cur ^ 1], tid);
+#pragma unroll
+        for (int i = 0; i < V; ++i) sa[i] = sa_n[i];
+#pragma unroll
+        for (int j = 0; j < H; ++j) sb[j] = sb_n[j];
         __syncthreads();
     }
 
@@ -283,6 +315,7 @@ const SgemmConfig kFp8Configs[] = {
     {1, 256, 128, 128, 128, 64},
     {2, 128, 128, 128, 64, 64},
     {3, 64, 64, 128, 32, 32},
+    {4, 256, 256, 128, 128, 64},
 };
 const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
 
@@ -293,6 +326,7 @@ hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
     case 1: return launch_fp8_cfg<256, 128, 128, 64>(g, stream);
     case 2: return launch_fp8_cfg<128, 128, 64, 64>(g, stream);
     case 3: return launch_fp8_cfg<64, 64, 32, 32>(g, stream);
+    case 4: return launch_fp8_cfg<256, 256, 128, 64>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -110,7 +110,7 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         return 3;
     }
     if (path == MG_PATH_FP8_T128) {
-        if (tiles(M, N, 256, 256) >= 256) return 0;
+        if (tiles(M, N, 256, 256) >= 256) return 4;
         if (tiles(M, N, 128, 128) >= 128) return 2;
         return 3;
     }

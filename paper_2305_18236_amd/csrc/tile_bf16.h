@@ -349,6 +349,10 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
                 for (int j = 0; j < H; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
+        // Keep the pack (which waits for this iteration's global loads) after
+        // the MFMAs: the compiler may otherwise hoist the LDS writes above
+        // them, since they target the other buffer.
+        __builtin_amdgcn_sched_barrier(0);
         if (PACK_AT == STEPS) pack(cur ^ 1);   // the last panel rewrites stale data nobody reads
         __syncthreads();
     }
