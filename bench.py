@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8"], default="sgemm",
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep"], default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
                          "chain: forward + backward of Y = (X W1) W2")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -166,6 +166,8 @@ def main():
         return bench_chain(args, torch, si, native, dev)
     if args.workload == "fp8":
         return bench_fp8(args, torch, si, native, dev)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -407,6 +409,50 @@ def bench_fp8(args, torch, si, native, dev):
            "gemm_only_tflops": round(flops / (t_gemm * 1e-3) / 1e12, 2),
            "gemm_only_pct_fp8_peak": round(100 * flops / (t_gemm * 1e-3) / 1e12 / PEAK_TFLOPS["fp8"], 2),
            "bf16_tflops": round(flops / (t_bf16 * 1e-3) / 1e12, 2)}
+    print(json.dumps(out), flush=True)
+
+
+SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+                (8192, 8192, 256), (256, 8192, 8192), (16384, 1024, 4096)]
+
+
+def bench_sweep(args, torch, si, native, dev):
+    """The FP32 sweep (alpha 1.5, beta 0.5, U[-1, 1]) in all four layouts on the
+    FP32 path, and NN on the bf16x3 path; one JSON line with a row per case."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    rows = []
+    for (m, n, k) in SWEEP_SHAPES:
+        A = torch.from_numpy(si.uniform((m * k,), si.seed_for(2, "A"))).to(dev)
+        B = torch.from_numpy(si.uniform((k * n,), si.seed_for(2, "B"))).to(dev)
+        C = torch.from_numpy(si.uniform((m * n,), si.seed_for(2, "C"))).to(dev)
+        flops = 2.0 * m * n * k
+        cases = [("fp32", tA, tB) for tA in "NT" for tB in "NT"] + [("bf16x3", "N", "N")]
+        for path, tA, tB in cases:
+            pid = {"fp32": 0, "bf16x3": 1}[path]
+            lda = k if tA == "N" else m
+            ldb = n if tB == "N" else k
+            need = native.mg_gemm_workspace_size(pid, tA, tB, m, n, k)
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+            def run():
+                native.check(native.mg_gemm(pid, tA, tB, m, n, k, ALPHA, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                            BETA, C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+
+            ms = _time_ms(run, args.steps, args.warmup, torch, stream)
+            tf = flops / (ms * 1e-3) / 1e12
+            rows.append({"M": m, "N": n, "K": k, "path": path, "layout": tA + tB, "ms": round(ms, 4),
+                         "tflops": round(tf, 2),
+                         "pct_fp32_peak": round(100 * tf / PEAK_TFLOPS["fp32"], 1) if path == "fp32" else None,
+                         "config": native.mg_tuned_config(pid, m, n, k)})
+        del A, B, C
+    nn8 = [r for r in rows if r["M"] == 8192 and r["K"] == 8192 and r["path"] == "fp32" and r["layout"] == "NN"][0]
+    out = {"metric": "FP32 SGEMM sweep TFLOP/s (all layouts) and bf16x3 NN", "unit": "TFLOP/s",
+           "value": nn8["tflops"], "ms_per_step": nn8["ms"], "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sgemm_sweep", "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]"},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

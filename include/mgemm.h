@@ -124,11 +124,12 @@ int mg_config_info(int path, int index, int *out6);
 int mg_force_config(int path, int config_id);
 
 /*
- * Tuning table written by the autotuner: text lines "path mb nb kb config",
- * where mb/nb/kb are round(log2(M/N/K)) (0..20) and config an id from
- * mg_config_info; '#' starts a comment.  A loaded table replaces the previous
- * one; NULL clears it.  Selection order for every GEMM: mg_force_config, then
- * the table, then the built-in rule.  Load it before launching GEMMs from
+ * Tuning table written by the autotuner: text lines "path mb nb kb config
+ * [mode]", where mb/nb/kb are round(log2(M/N/K)) (0..20), config an id from
+ * mg_config_info and mode 's' (single GEMMs, the default) or 'b' (the batched
+ * kernel, which falls back to 's' entries); '#' starts a comment.  A loaded
+ * table replaces the previous one; NULL clears it.  Selection order for every
+ * GEMM: mg_force_config, then the table, then the built-in rule.  Load it before launching GEMMs from
  * other threads.  Returns MG_ERR_BAD_TABLE (previous table kept) for an
  * unreadable or malformed file.
  */

@@ -102,7 +102,8 @@ def tune(paths=("fp32", "bf16x3", "bf16"), mode="batched", buckets=range(5, 12),
     dev = torch.device("cuda:0")
     _native.lib()
     bench = _Bench(torch, dev)
-    lines = ["# mgemm tuning table: path mb nb kb config (mb/nb/kb = round(log2 M/N/K))",
+    lines = ["# mgemm tuning table: path mb nb kb config mode (mb/nb/kb = round(log2 M/N/K);",
+             "# mode b: read by the batched kernel, s: by single GEMMs)",
              f"# mode {mode}, written by paper_2305_18236_amd.autotune on {time.strftime('%Y-%m-%d')}"]
     t0 = time.time()
     for path in paths:
@@ -128,7 +129,7 @@ def tune(paths=("fp32", "bf16x3", "bf16"), mode="batched", buckets=range(5, 12),
                             _native.mg_force_config(pid, -1)
                         if ms < best_t:
                             best, best_t = cid, ms
-                    lines.append(f"{pid} {mb} {nb} {kb} {best}")
+                    lines.append(f"{pid} {mb} {nb} {kb} {best} {'b' if mode == 'batched' else 's'}")
                     tflops = 2.0 * M * N * K * copies / (best_t * 1e-3) / 1e12
                     print(f"{path} M{M} N{N} K{K} x{copies}: config {best} {best_t * 1e3:.1f} us "
                           f"{tflops:.1f} TFLOP/s", file=log, flush=True)

@@ -70,11 +70,12 @@ ConfigTable table_of(int path)
     }
 }
 
-// ---- Tuning table: (path, bucket(M), bucket(N), bucket(K)) -> configuration
-// id, written by the autotuner.  bucket(x) = round(log2 x), clamped to
-// [0, kBuckets).  -1 means "not tuned".
+// ---- Tuning table: (mode, path, bucket(M), bucket(N), bucket(K)) ->
+// configuration id, written by the autotuner.  mode 0 ('s') is read by single
+// GEMMs, mode 1 ('b') by the batched kernel (which falls back to mode 0).
+// bucket(x) = round(log2 x), clamped to [0, kBuckets).  -1: not tuned.
 constexpr int kBuckets = 21;
-int8_t g_table[4][kBuckets][kBuckets][kBuckets];
+int8_t g_table[2][4][kBuckets][kBuckets][kBuckets];
 std::once_flag g_table_init;
 std::mutex g_table_mutex;
 
@@ -91,10 +92,10 @@ int bucket(int64_t x)
     return b < kBuckets ? b : kBuckets - 1;
 }
 
-int table_lookup(int path, int64_t M, int64_t N, int64_t K)
+int table_lookup(int path, int64_t M, int64_t N, int64_t K, int mode = 0)
 {
     std::call_once(g_table_init, table_clear);
-    return g_table[path][bucket(M)][bucket(N)][bucket(K)];
+    return g_table[mode][path][bucket(M)][bucket(N)][bucket(K)];
 }
 
 // Automatic configuration: the largest workgroup tile that still gives every
@@ -276,7 +277,8 @@ int choose_batched_variant(int path, int64_t M, int64_t N, int64_t K)
     const int* cfgs = batched_cfgs(path);
     const int nv = batched_count(path);
     int tuned = g_forced[path].load();
-    if (tuned < 0) tuned = table_lookup(path, M, N, K);
+    if (tuned < 0) tuned = table_lookup(path, M, N, K, 1);
+    if (tuned < 0) tuned = table_lookup(path, M, N, K, 0);
     for (int v = 0; v < nv; ++v)
         if (cfgs[v] == tuned) return v;
     if (M >= 128 && N >= 128) return nv - 1;   // 128 x 128
@@ -453,7 +455,7 @@ int mg_load_tuning(const char* path)
     }
     FILE* f = std::fopen(path, "r");
     if (!f) return MG_ERR_BAD_TABLE;
-    static int8_t fresh[4][kBuckets][kBuckets][kBuckets];
+    static int8_t fresh[2][4][kBuckets][kBuckets][kBuckets];
     std::memset(fresh, -1, sizeof(fresh));
     char line[256];
     int bad = 0;
@@ -462,13 +464,15 @@ int mg_load_tuning(const char* path)
         while (*q == ' ' || *q == '\t') ++q;
         if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
         int p, mb, nb, kb, cfg;
-        if (std::sscanf(q, "%d %d %d %d %d", &p, &mb, &nb, &kb, &cfg) != 5 || p < 0 || p > 3 ||
-            mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 || kb >= kBuckets ||
-            cfg < 0 || cfg >= table_of(p).n) {
+        char mode[8] = "s";
+        const int got = std::sscanf(q, "%d %d %d %d %d %7s", &p, &mb, &nb, &kb, &cfg, mode);
+        if (got < 5 || p < 0 || p > 3 || mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 ||
+            kb >= kBuckets || cfg < 0 || cfg >= table_of(p).n || !(mode[0] == 's' || mode[0] == 'b') ||
+            mode[1] != 0) {
             bad = 1;
             break;
         }
-        fresh[p][mb][nb][kb] = int8_t(cfg);
+        fresh[mode[0] == 'b' ? 1 : 0][p][mb][nb][kb] = int8_t(cfg);
     }
     std::fclose(f);
     if (bad) return MG_ERR_BAD_TABLE;

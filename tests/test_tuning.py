@@ -47,7 +47,25 @@ def test_table_selection_order(native, tmp_path):
     assert native.mg_tuned_config(0, 8192, 8192, 8192) == untuned
 
 
-@pytest.mark.parametrize("text", ["0 8 8 8\n", "0 8 8 8 99\n", "7 8 8 8 0\n", "0 30 8 8 0\n", "x y z\n"])
+def test_batched_entries_do_not_steer_single_gemms(native, tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text("0 8 8 8 3 b\n1 8 8 8 4 b\n")
+    assert native.mg_load_tuning(str(p)) == 0
+    assert native.mg_batched_config(0, 256, 256, 256) == 3
+    assert native.mg_batched_config(1, 256, 256, 256) == 4
+    native.mg_load_tuning(None)
+    untuned = native.mg_tuned_config(0, 256, 256, 256)
+    assert native.mg_load_tuning(str(p)) == 0
+    assert native.mg_tuned_config(0, 256, 256, 256) == untuned
+    # an 's' entry steers single GEMMs, and the batched kernel when it is a batched variant
+    p.write_text("0 8 8 8 3 s\n")
+    assert native.mg_load_tuning(str(p)) == 0
+    assert native.mg_tuned_config(0, 256, 256, 256) == 3
+    assert native.mg_batched_config(0, 256, 256, 256) == 3
+
+
+@pytest.mark.parametrize("text", ["0 8 8 8\n", "0 8 8 8 99\n", "7 8 8 8 0\n", "0 30 8 8 0\n", "x y z\n",
+                                  "0 8 8 8 3 q\n", "0 8 8 8 3 bb\n"])
 def test_malformed_table_rejected_and_previous_kept(native, tmp_path, text):
     good = tmp_path / "good.txt"
     good.write_text("0 8 8 8 3\n")
