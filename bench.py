@@ -418,34 +418,38 @@ SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (819
 
 def bench_sweep(args, torch, si, native, dev):
     """The FP32 sweep (alpha 1.5, beta 0.5, U[-1, 1]) in all four layouts on the
-    FP32 path, and NN on the bf16x3 path; one JSON line with a row per case."""
+    FP32 path, then NN on the bf16x3 path; one JSON line with a row per case.
+    The bf16x3 cases run after every FP32 case: the chip clocks down under
+    sustained BF16 matrix work and takes a while to recover, which would
+    otherwise be charged to the FP32 case that follows."""
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     rows = []
-    for (m, n, k) in SWEEP_SHAPES:
-        A = torch.from_numpy(si.uniform((m * k,), si.seed_for(2, "A"))).to(dev)
-        B = torch.from_numpy(si.uniform((k * n,), si.seed_for(2, "B"))).to(dev)
-        C = torch.from_numpy(si.uniform((m * n,), si.seed_for(2, "C"))).to(dev)
-        flops = 2.0 * m * n * k
-        cases = [("fp32", tA, tB) for tA in "NT" for tB in "NT"] + [("bf16x3", "N", "N")]
-        for path, tA, tB in cases:
-            pid = {"fp32": 0, "bf16x3": 1}[path]
-            lda = k if tA == "N" else m
-            ldb = n if tB == "N" else k
-            need = native.mg_gemm_workspace_size(pid, tA, tB, m, n, k)
-            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    for path, layouts in (("fp32", [tA + tB for tA in "NT" for tB in "NT"]), ("bf16x3", ["NN"])):
+        pid = {"fp32": 0, "bf16x3": 1}[path]
+        for (m, n, k) in SWEEP_SHAPES:
+            A = torch.from_numpy(si.uniform((m * k,), si.seed_for(2, "A"))).to(dev)
+            B = torch.from_numpy(si.uniform((k * n,), si.seed_for(2, "B"))).to(dev)
+            C = torch.from_numpy(si.uniform((m * n,), si.seed_for(2, "C"))).to(dev)
+            flops = 2.0 * m * n * k
+            for tA, tB in layouts:
+                lda = k if tA == "N" else m
+                ldb = n if tB == "N" else k
+                need = native.mg_gemm_workspace_size(pid, tA, tB, m, n, k)
+                ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
 
-            def run():
-                native.check(native.mg_gemm(pid, tA, tB, m, n, k, ALPHA, A.data_ptr(), lda, B.data_ptr(), ldb,
-                                            BETA, C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+                def run():
+                    native.check(native.mg_gemm(pid, tA, tB, m, n, k, ALPHA, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                                BETA, C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
 
-            ms = _time_ms(run, args.steps, args.warmup, torch, stream)
-            tf = flops / (ms * 1e-3) / 1e12
-            rows.append({"M": m, "N": n, "K": k, "path": path, "layout": tA + tB, "ms": round(ms, 4),
-                         "tflops": round(tf, 2),
-                         "pct_fp32_peak": round(100 * tf / PEAK_TFLOPS["fp32"], 1) if path == "fp32" else None,
-                         "config": native.mg_tuned_config(pid, m, n, k)})
-        del A, B, C
+                ms = _time_ms(run, args.steps, args.warmup, torch, stream)
+                tf = flops / (ms * 1e-3) / 1e12
+                rows.append({"M": m, "N": n, "K": k, "path": path, "layout": tA + tB, "ms": round(ms, 4),
+                             "tflops": round(tf, 2),
+                             "pct_fp32_peak": round(100 * tf / PEAK_TFLOPS["fp32"], 1) if path == "fp32" else None,
+                             "config": native.mg_tuned_config(pid, m, n, k),
+                             "splits": native.mg_split_count(pid, m, n, k)})
+            del A, B, C
     nn8 = [r for r in rows if r["M"] == 8192 and r["K"] == 8192 and r["path"] == "fp32" and r["layout"] == "NN"][0]
     out = {"metric": "FP32 SGEMM sweep TFLOP/s (all layouts) and bf16x3 NN", "unit": "TFLOP/s",
            "value": nn8["tflops"], "ms_per_step": nn8["ms"], "n_gpus": 1, "steps": args.steps,

@@ -92,18 +92,27 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
              float beta, float *C, int64_t ldc, void *stream);
 
 /*
- * GEMM on the given path.  `workspace` (device memory, caller-owned, at least
- * mg_gemm_workspace_size() bytes, 256-byte aligned) holds the packed FP8
- * operands on MG_PATH_FP8_T128; the other paths need none (NULL, 0 is fine).
- * Returns MG_ERR_WORKSPACE if it is too small, MG_ERR_UNSUPPORTED for an
- * unknown path.
+ * GEMM on the given path.  `workspace` is device memory, caller-owned,
+ * 256-byte aligned, of mg_gemm_workspace_size() bytes.  It holds:
+ *   - MG_PATH_FP8_T128: the packed FP8 operands (required: MG_ERR_WORKSPACE
+ *     if missing or too small);
+ *   - MG_PATH_BF16 with M, N >= 512: the operands rounded to bf16 once;
+ *   - every other path: the partial products of a split-K launch, used when
+ *     the problem has fewer output tiles than the GPU has compute units and
+ *     K >= 256 (the K loop is cut into ranges multiplied by separate
+ *     workgroups, then summed in a fixed order, so results stay deterministic).
+ * On the non-FP8 paths the workspace is optional: with NULL or too few bytes
+ * the GEMM runs without the optimisation that needed it.  Returns
+ * MG_ERR_UNSUPPORTED for an unknown path.  Concurrent calls must not share a
+ * workspace.
  */
 int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
             float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
             float beta, float *C, int64_t ldc,
             void *workspace, size_t workspace_bytes, void *stream);
 
-/* Workspace bytes mg_gemm needs for this problem (0 when none). */
+/* Workspace bytes mg_gemm uses for this problem with the current selection
+ * state (forced configuration, tuning table, forced split; 0 when none). */
 size_t mg_gemm_workspace_size(int path, char transA, char transB,
                               int64_t M, int64_t N, int64_t K);
 
@@ -122,6 +131,16 @@ int mg_config_info(int path, int index, int *out6);
  * return to automatic selection.  Process-wide; meant for the autotuner.
  */
 int mg_force_config(int path, int config_id);
+
+/*
+ * Force the split-K factor of `path`: 1 never splits, 2..16 cuts K into (at
+ * most) that many ranges of a multiple of 128 when K >= 256, -1 returns to the
+ * automatic rule.  Process-wide; meant for the autotuner and tests.
+ * mg_split_count gives the number of K ranges a GEMM of this shape would use
+ * now (given a large enough workspace).
+ */
+int mg_force_splits(int path, int splits);
+int mg_split_count(int path, int64_t M, int64_t N, int64_t K);
 
 /*
  * Tuning table written by the autotuner: text lines "path mb nb kb config

@@ -54,6 +54,10 @@ def lib():
     L.mg_config_info.restype = ci
     L.mg_force_config.argtypes = [ci, ci]
     L.mg_force_config.restype = ci
+    L.mg_force_splits.argtypes = [ci, ci]
+    L.mg_force_splits.restype = ci
+    L.mg_split_count.argtypes = [ci, i64, i64, i64]
+    L.mg_split_count.restype = ci
     L.mg_bf16_split.argtypes = [vp, i64, vp, vp, vp]
     L.mg_bf16_split.restype = ci
     sz = ctypes.c_size_t
@@ -177,3 +181,11 @@ def mg_config_info(path, index):
 
 def mg_force_config(path, config_id) -> int:
     return int(lib().mg_force_config(int(path), int(config_id)))
+
+
+def mg_force_splits(path, splits) -> int:
+    return int(lib().mg_force_splits(int(path), int(splits)))
+
+
+def mg_split_count(path, M, N, K) -> int:
+    return int(lib().mg_split_count(int(path), M, N, K))

@@ -33,7 +33,36 @@ struct GemmArgs {
     // Pre-packed BF16 operands only: element offset from the hi plane of
     // op(A) (op(B)^T) to its lo plane.
     int64_t plane_a, plane_b;
+    // Split-K (launched with gridDim.y > 1): workgroup row s of the grid
+    // multiplies the K range [s*k_chunk, min(K, (s+1)*k_chunk)) and stores its
+    // unscaled partial product at part + s*part_stride (row stride ldp, a
+    // multiple of 4, 16-byte aligned); splitk_reduce_kernel then sums the
+    // partials in order of s and applies alpha and beta.
+    float* part;
+    int64_t k_chunk, ldp, part_stride;
 };
+
+// The GEMM one workgroup of a split-K launch computes (see GemmArgs::part).
+// PACKED: A and B are k-contiguous bf16 rows (the pre-packed planes).
+template <bool TA, bool TB, bool PACKED>
+MG_DEVICE void split_k_view(GemmArgs& g)
+{
+    if (gridDim.y == 1) return;
+    const int64_t k0 = int64_t(blockIdx.y) * g.k_chunk;
+    g.K = min(g.k_chunk, g.K - k0);
+    if (PACKED) {
+        g.A = reinterpret_cast<const float*>(reinterpret_cast<const uint16_t*>(g.A) + k0);
+        g.B = reinterpret_cast<const float*>(reinterpret_cast<const uint16_t*>(g.B) + k0);
+    } else {
+        g.A += TA ? k0 * g.lda : k0;
+        g.B += TB ? k0 : k0 * g.ldb;
+    }
+    g.C = g.part + int64_t(blockIdx.y) * g.part_stride;
+    g.ldc = g.ldp;
+    g.alpha = 1.f;
+    g.beta = 0.f;
+    g.vec_c = 1;
+}
 
 // Arguments of the FP8 GEMM on packed operands (see gemm_fp8.hip).
 struct Fp8Args {

@@ -7,9 +7,11 @@ namespace mg {
 
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int TERMS>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
-void gemm_bf16_kernel(GemmArgs g)
+void gemm_bf16_kernel(GemmArgs args)
 {
     __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<BM, BN, BK, TERMS>()];
+    GemmArgs g = args;
+    split_k_view<TA, TB, false>(g);
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     bf16_tile<BM, BN, BK, WM, WN, TA, TB, TERMS>(g, tm, tn, smem);
@@ -19,9 +21,11 @@ void gemm_bf16_kernel(GemmArgs g)
 // checks on loads; the epilogue still clips to M x N).
 template <int BM, int BN, int BK, int WM, int WN, int TERMS>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
-void gemm_bf16_packed_kernel(GemmArgs g)
+void gemm_bf16_packed_kernel(GemmArgs args)
 {
     __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<BM, BN, BK, TERMS>()];
+    GemmArgs g = args;
+    split_k_view<false, true, true>(g);
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS, true>(g, tm, tn, smem);
@@ -33,7 +37,7 @@ static hipError_t launch_bf16_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stre
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
-    const dim3 grid(g.tiles_m * g.tiles_n), block(NT);
+    const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
     if (packed) hipLaunchKernelGGL((gemm_bf16_packed_kernel<BM, BN, BK, WM, WN, TERMS>), grid, block, 0, stream, g);
     else if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, false, false, TERMS>), grid, block, 0, stream, g);
     else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, WM, WN, false, true, TERMS>), grid, block, 0, stream, g);

@@ -7,9 +7,11 @@ namespace mg {
 
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
-void sgemm_mfma_kernel(GemmArgs g)
+void sgemm_mfma_kernel(GemmArgs args)
 {
     __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<BM, BN, BK>()];
+    GemmArgs g = args;
+    split_k_view<TA, TB, false>(g);
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     sgemm_tile<BM, BN, BK, WM, WN, TA, TB>(g, tm, tn, smem);
@@ -24,7 +26,7 @@ static hipError_t launch_sgemm_cfg(bool ta, bool tb, GemmArgs g, hipStream_t str
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
-    const dim3 grid(g.tiles_m * g.tiles_n), block(NT);
+    const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
     if (!ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, false>), grid, block, 0, stream, g);
     else if (!ta && tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, true>), grid, block, 0, stream, g);
     else if (ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, false>), grid, block, 0, stream, g);
@@ -72,6 +74,59 @@ __global__ __launch_bounds__(256) void scale_c_kernel(float* C, int64_t M, int64
         float* p = C + i * ldc + j;
         *p = (beta == 0.f) ? 0.f : beta * *p;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction: C = alpha * (P_0 + P_1 + ... + P_{S-1}) + beta * C0, the
+// partials summed in order of s (so results do not depend on scheduling) and
+// the epilogue formula of the tile kernels applied to the sum.  Each thread
+// handles four consecutive columns of one row per step.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int64_t ldp,
+                                                            int64_t stride, int S, float* C, int64_t ldc,
+                                                            int64_t M, int64_t N, float alpha, float beta,
+                                                            int vec_c)
+{
+    const int64_t n4 = (N + 3) / 4;
+    const int64_t total = M * n4;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = t / n4, j = (t - i * n4) * 4;
+        const float* p = part + i * ldp + j;
+        floatx4 acc = *reinterpret_cast<const floatx4*>(p);
+        for (int s = 1; s < S; ++s) {
+            const floatx4 x = *reinterpret_cast<const floatx4*>(p + s * stride);
+            acc[0] += x[0]; acc[1] += x[1]; acc[2] += x[2]; acc[3] += x[3];
+        }
+        float* c = C + i * ldc + j;
+        if (vec_c && j + 3 < N) {
+            floatx4 o = {alpha * acc[0], alpha * acc[1], alpha * acc[2], alpha * acc[3]};
+            if (beta != 0.f) {
+                const floatx4 c0 = *reinterpret_cast<const floatx4*>(c);
+                o[0] = __builtin_fmaf(alpha, acc[0], beta * c0[0]);
+                o[1] = __builtin_fmaf(alpha, acc[1], beta * c0[1]);
+                o[2] = __builtin_fmaf(alpha, acc[2], beta * c0[2]);
+                o[3] = __builtin_fmaf(alpha, acc[3], beta * c0[3]);
+            }
+            *reinterpret_cast<floatx4*>(c) = o;
+        } else {
+            for (int e = 0; e < 4 && j + e < N; ++e) {
+                float o = alpha * acc[e];
+                if (beta != 0.f) o = __builtin_fmaf(alpha, acc[e], beta * c[e]);
+                c[e] = o;
+            }
+        }
+    }
+}
+
+hipError_t launch_splitk_reduce(const GemmArgs& g, int splits, float* C, int64_t ldc, hipStream_t stream)
+{
+    const int64_t total = g.M * ((g.N + 3) / 4);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    const int vec_c = (reinterpret_cast<uintptr_t>(C) & 15) == 0 && ldc % 4 == 0;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, g.part, g.ldp,
+                       g.part_stride, splits, C, ldc, g.M, g.N, g.alpha, g.beta, vec_c);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream)

@@ -61,4 +61,13 @@ int batched_blocks_per_cu(int path);
 
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
+// Number of K ranges of a split-K launch described by g (1: no split).
+inline unsigned split_count(const GemmArgs& g)
+{
+    return g.k_chunk > 0 ? unsigned((g.K + g.k_chunk - 1) / g.k_chunk) : 1u;
+}
+
+// Sums the `splits` partials of g.part into C with g.alpha / g.beta.
+hipError_t launch_splitk_reduce(const GemmArgs& g, int splits, float* C, int64_t ldc, hipStream_t stream);
+
 }  // namespace mg

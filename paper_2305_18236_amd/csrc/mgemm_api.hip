@@ -19,6 +19,7 @@ bool is_n(char t) { return t == 'N' || t == 'n'; }
 bool is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 
 std::atomic<int> g_forced[4] = {{-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_forced_splits[4] = {{-1}, {-1}, {-1}, {-1}};
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP - int(e); }
 
@@ -98,28 +99,53 @@ int table_lookup(int path, int64_t M, int64_t N, int64_t K, int mode = 0)
     return g_table[mode][path][bucket(M)][bucket(N)][bucket(K)];
 }
 
-// Automatic configuration: the largest workgroup tile that still gives every
-// compute unit at least one tile; smaller problems fall back to smaller tiles
-// so that more of the 256 CUs take part.
+int device_cus();
+
+// ---- Split-K: when a GEMM has fewer output tiles than the GPU has compute
+// units, the K loop is cut into ranges that separate workgroups multiply; the
+// partial products go to the workspace and a reduction kernel sums them in a
+// fixed order and applies alpha and beta.
+constexpr int64_t kSplitGrain = 128;   // K range granularity (multiple of every BK)
+constexpr int64_t kMinRange = 256;     // shortest K range the rule cuts
+constexpr int kMaxSplits = 16;
+
+// Split factor the automatic rule gives `t` output tiles: enough K ranges for
+// one workgroup per compute unit, each at least kMinRange deep.
+int auto_splits(int64_t t, int64_t K)
+{
+    const int64_t cus = device_cus();
+    if (t >= cus) return 1;
+    const int64_t s = std::min<int64_t>({(cus + t - 1) / t, K / kMinRange, kMaxSplits});
+    return s < 2 ? 1 : int(s);
+}
+
+// Automatic configuration.  Measured on MI355X (FP32 and bf16x3 sweeps over
+// 1024^3 .. 8192^3 and skinny shapes): the 256 x 256 tile is the most
+// efficient whenever the tiles, times the split factor, give every compute
+// unit a workgroup; otherwise the next smaller tile with its split.  Very
+// short K (<= 256) favours 64 x 64 tiles, several per compute unit, whose
+// epilogues overlap other workgroups' matrix work.
 int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
-    (void)K;
-    if (path == MG_PATH_FP32) {
-        if (tiles(M, N, 256, 256) >= 256) return 5;
-        if (tiles(M, N, 256, 128) >= 256) return 2;
-        if (tiles(M, N, 128, 128) >= 128) return 0;
-        return 3;
-    }
+    const int64_t cus = device_cus();
     if (path == MG_PATH_FP8_T128) {
         if (tiles(M, N, 256, 256) >= 256) return 4;
         if (tiles(M, N, 128, 128) >= 128) return 2;
         return 3;
     }
     if (path == MG_PATH_BF16 && tiles(M, N, 128, 128) >= 1024) return 2;   // pre-packed: 128 x 128 best
-    if (tiles(M, N, 256, 256) >= 256) return 1;
-    if (tiles(M, N, 256, 128) >= 256) return 3;
-    if (tiles(M, N, 128, 128) >= 128) return 2;
-    return 4;
+    // tile ids by decreasing size: 256 x 256, 128 x 128, 64 x 64
+    static const int kFp32Ladder[3] = {5, 0, 3};
+    static const int kBf16Ladder[3] = {1, 2, 4};
+    const int* ladder = path == MG_PATH_FP32 ? kFp32Ladder : kBf16Ladder;
+    const ConfigTable t = table_of(path);
+    if (K <= 256 && tiles(M, N, 64, 64) >= cus) return ladder[2];
+    for (int i = 0; i < 3; ++i) {
+        const mg::SgemmConfig& c = t.cfgs[ladder[i]];
+        const int64_t n = tiles(M, N, c.bm, c.bn);
+        if (n * auto_splits(n, K) >= cus) return ladder[i];
+    }
+    return ladder[2];
 }
 
 int pick_config(int path, int64_t M, int64_t N, int64_t K);
@@ -181,6 +207,29 @@ Bf16Workspace bf16_workspace(int path, int64_t M, int64_t N, int64_t K)
     return w;
 }
 
+struct SplitPlan {
+    int splits;          // 1: no split
+    int64_t chunk, ldp, stride;
+    size_t bytes;
+};
+
+SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
+{
+    SplitPlan p{1, 0, 0, 0, 0};
+    if (path == MG_PATH_FP8_T128 || M <= 0 || N <= 0 || K < 2 * kSplitGrain) return p;
+    const mg::SgemmConfig& c = table_of(path).cfgs[cfg];
+    int s = g_forced_splits[path].load();
+    if (s < 0) s = auto_splits(tiles(M, N, c.bm, c.bn), K);
+    if (s < 2) return p;
+    p.chunk = round_up((K + s - 1) / s, kSplitGrain);
+    p.splits = int((K + p.chunk - 1) / p.chunk);
+    if (p.splits < 2) return SplitPlan{1, 0, 0, 0, 0};
+    p.ldp = round_up(N, 4);
+    p.stride = M * p.ldp;
+    p.bytes = align256(size_t(p.splits) * size_t(p.stride) * sizeof(float));
+    return p;
+}
+
 int run_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* qA, const uint8_t* sA,
                    const uint8_t* qB, const uint8_t* sB, float beta, float* C, int64_t ldc,
                    hipStream_t stream)
@@ -213,11 +262,13 @@ int pick_config(int path, int64_t M, int64_t N, int64_t K)
     return choose_config(path, M, N, K);
 }
 
+// split_ws: workspace for the partial products of a split-K plan (nullptr:
+// no split).  bf16_planes: workspace for pre-packed BF16 operands.
 int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
              const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
-             int64_t ldc, hipStream_t stream, void* bf16_planes = nullptr)
+             int64_t ldc, hipStream_t stream, int cfg, const SplitPlan& plan, void* split_ws,
+             void* bf16_planes)
 {
-    const int cfg = pick_config(path, M, N, K);
     const ConfigTable t = table_of(path);
     const mg::SgemmConfig& c = t.cfgs[cfg];
     if (tiles(M, N, c.bm, c.bn) > INT_MAX) return MG_ERR_TOO_LARGE;
@@ -230,12 +281,23 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     g.vec_a = fast_operand(A, lda);
     g.vec_b = fast_operand(B, ldb);
     g.vec_c = aligned16(C) && ldc % 4 == 0;
+    const bool split = split_ws != nullptr && plan.splits > 1;
+    if (split) {
+        g.part = static_cast<float*>(split_ws);
+        g.k_chunk = plan.chunk;
+        g.ldp = plan.ldp;
+        g.part_stride = plan.stride;
+    }
+    auto finish = [&](hipError_t e) {
+        if (e != hipSuccess || !split) return hip_status(e);
+        return hip_status(mg::launch_splitk_reduce(g, plan.splits, C, ldc, stream));
+    };
     switch (path) {
-    case MG_PATH_FP32: return hip_status(mg::launch_sgemm(cfg, ta, tb, g, stream));
+    case MG_PATH_FP32: return finish(mg::launch_sgemm(cfg, ta, tb, g, stream));
     case MG_PATH_BF16X3:
     case MG_PATH_BF16: {
         const int terms = path == MG_PATH_BF16X3 ? 3 : 1;
-        if (bf16_planes == nullptr) return hip_status(mg::launch_gemm_bf16(terms, cfg, ta, tb, g, stream));
+        if (bf16_planes == nullptr) return finish(mg::launch_gemm_bf16(terms, cfg, ta, tb, g, stream));
         // pack each operand once, then multiply the packed planes
         const Bf16Workspace w = bf16_workspace(path, M, N, K);
         uint8_t* base = static_cast<uint8_t*>(bf16_planes);
@@ -255,7 +317,7 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
         g.lda = g.ldb = w.Kp;
         g.plane_a = int64_t(w.a_lo - w.a_hi) / 2;
         g.plane_b = int64_t(w.b_lo - w.b_hi) / 2;
-        return hip_status(mg::launch_gemm_bf16(terms, cfg, false, true, g, stream, true));
+        return finish(mg::launch_gemm_bf16(terms, cfg, false, true, g, stream, true));
     }
     default: return MG_ERR_UNSUPPORTED;
     }
@@ -340,11 +402,24 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
         return run_fp8_packed(M, N, K, alpha, base + w.qa, base + w.sa, base + w.qb, base + w.sb,
                               beta, C, ldc, s);
     }
+    // Optional workspace uses, in this order: pre-packed BF16 planes, then the
+    // split-K partials; each is used only if the workspace still has room.
+    const int cfg = pick_config(path, M, N, K);
+    const SplitPlan plan = split_plan(path, cfg, M, N, K);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    size_t left = (ws != nullptr && (reinterpret_cast<uintptr_t>(ws) & 255) == 0) ? workspace_bytes : 0;
     void* planes = nullptr;
-    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K) && workspace != nullptr &&
-        workspace_bytes >= bf16_workspace(path, M, N, K).total && (reinterpret_cast<uintptr_t>(workspace) & 255) == 0)
-        planes = workspace;
-    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, planes);
+    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K)) {
+        const size_t need = align256(bf16_workspace(path, M, N, K).total);
+        if (left >= need) {
+            planes = ws;
+            ws += need;
+            left -= need;
+        }
+    }
+    void* split_ws = (plan.splits > 1 && left >= plan.bytes) ? ws : nullptr;
+    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, cfg,
+                    plan, split_ws, planes);
 }
 
 int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
@@ -358,11 +433,13 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
 {
     (void)transA; (void)transB;
-    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (M <= 0 || N <= 0 || K <= 0 || table_of(path).n == 0) return 0;
     if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
+    size_t total = 0;
     if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K))
-        return bf16_workspace(path, M, N, K).total;
-    return 0;
+        total += align256(bf16_workspace(path, M, N, K).total);
+    total += split_plan(path, pick_config(path, M, N, K), M, N, K).bytes;
+    return total;
 }
 
 int mg_fp8_packed_size(int64_t R, int64_t K, size_t* q_bytes, size_t* scale_bytes)
@@ -434,6 +511,20 @@ int mg_force_config(int path, int config_id)
     if (config_id < -1 || config_id >= mg_num_configs(path)) return MG_ERR_UNSUPPORTED;
     g_forced[path].store(config_id);
     return MG_OK;
+}
+
+int mg_force_splits(int path, int splits)
+{
+    if (path < 0 || path > 3) return MG_ERR_UNSUPPORTED;
+    if (splits < -1 || splits == 0 || splits > kMaxSplits) return MG_ERR_UNSUPPORTED;
+    g_forced_splits[path].store(splits);
+    return MG_OK;
+}
+
+int mg_split_count(int path, int64_t M, int64_t N, int64_t K)
+{
+    if (table_of(path).n == 0 || M <= 0 || N <= 0 || K <= 0) return 1;
+    return split_plan(path, pick_config(path, M, N, K), M, N, K).splits;
 }
 
 int mg_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* stream)

@@ -33,12 +33,28 @@
 // single 4*V-byte LDS access over contiguous addresses (no bank conflicts) and
 // lets the epilogue write H consecutive columns per lane.
 //
+// Bank swizzle.  Panel rows are BM or BN floats, a multiple of the 64 LDS
+// banks, so without a remedy the transposing pack (a K-contiguous source,
+// e.g. op(A) = A stored M x K) writes four k-rows at the same banks.  The
+// m (n) offset of every element of row k is therefore XORed with
+// panel_swizzle(k), a multiple of 64 / (BK/4) below 64 that changes with k/4:
+// the 64 lanes of one pack store then hit 64 distinct banks, while every
+// aligned group of 4 consecutive m (n) stays together (the fragment reads and
+// the 16-byte k-major stores are unchanged in shape).
+//
 // MFMA 32x32x2 f32 operand layout (per lane l of 64): A supplies
 // op(A)[row l%32][k l/32], B supplies op(B)[k l/32][col l%32]; result register
 // r of lane l is C[row 8*(r/4) + 4*(l/32) + r%4][col l%32].
 #include "common.h"
 
 namespace mg {
+
+template <int BK>
+MG_DEVICE constexpr int panel_swizzle(int k)
+{
+    constexpr int NC = BK / 4;   // 4-float chunks per stored row of a transposing panel
+    return ((k >> 2) % NC) * (64 / NC);
+}
 
 // ---------------------------------------------------------------------------
 // Global -> register staging of one panel, in the stored layout.
@@ -81,26 +97,28 @@ struct PanelLoader {
         }
     }
 
-    // Write into a k-major LDS panel with row length L (floats).
-    // kmajor_src: the stored rows are k (stored columns are m or n), so a chunk
-    // is four consecutive m/n of one k row and is written as one 16-byte store.
-    // Otherwise the stored rows are m/n and a chunk is four consecutive k of
-    // one m/n: it is transposed into four 4-byte stores.
+    // Write into a k-major LDS panel with row length L (floats), swizzled by
+    // panel_swizzle.  kmajor_src: the stored rows are k (stored columns are m
+    // or n), so a chunk is four consecutive m/n of one k row and is written as
+    // one 16-byte store.  Otherwise the stored rows are m/n and a chunk is four
+    // consecutive k of one m/n: it is transposed into four 4-byte stores.
     template <bool KMAJOR_SRC, int L>
     MG_DEVICE void store(float* lds, int tid) const
     {
+        constexpr int BK = KMAJOR_SRC ? SR : SC;
 #pragma unroll
         for (int s = 0; s < PER_THREAD; ++s) {
             const int q = tid + s * NT;
             const int r = q / (SC / 4);
             const int c = (q % (SC / 4)) * 4;
             if (KMAJOR_SRC) {
-                *reinterpret_cast<floatx4*>(lds + r * L + c) = v[s];
+                *reinterpret_cast<floatx4*>(lds + r * L + (c ^ panel_swizzle<BK>(r))) = v[s];
             } else {
-                lds[(c + 0) * L + r] = v[s][0];
-                lds[(c + 1) * L + r] = v[s][1];
-                lds[(c + 2) * L + r] = v[s][2];
-                lds[(c + 3) * L + r] = v[s][3];
+                const int m = r ^ panel_swizzle<BK>(c);   // same for k = c .. c+3
+                lds[(c + 0) * L + m] = v[s][0];
+                lds[(c + 1) * L + m] = v[s][1];
+                lds[(c + 2) * L + m] = v[s][2];
+                lds[(c + 3) * L + m] = v[s][3];
             }
         }
     }
@@ -194,21 +212,25 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
         const int cur = kt & 1;
         if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
 
-        const float* a_base = As[cur] + wm0 + V * c;
-        const float* b_base = Bs[cur] + wn0 + H * c;
+        const float* a_rows = As[cur] + h * BM;
+        const float* b_rows = Bs[cur] + h * BN;
+        const int am = wm0 + V * c, bnn = wn0 + H * c;
+        // Rows k = 2s and 2s+1 share their swizzle (it changes with k/4), so
+        // the swizzle of a step is a compile-time constant.
+        auto a_at = [&](int s) { return a_rows + 2 * s * BM + (am ^ panel_swizzle<BK>(2 * s)); };
+        auto b_at = [&](int s) { return b_rows + 2 * s * BN + (bnn ^ panel_swizzle<BK>(2 * s)); };
         // Software pipeline: the fragments of step s+1 are read from LDS
         // before the MFMAs of step s are issued, into separate registers, so
         // LDS latency hides behind the matrix core.
         float a[V], b[H];
-        lds_read<V>(a_base + h * BM, a);
-        lds_read<H>(b_base + h * BN, b);
+        lds_read<V>(a_at(0), a);
+        lds_read<H>(b_at(0), b);
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
             float an[V], bn[H];
             if (s + 1 < STEPS) {
-                const int k = 2 * (s + 1) + h;
-                lds_read<V>(a_base + k * BM, an);
-                lds_read<H>(b_base + k * BN, bn);
+                lds_read<V>(a_at(s + 1), an);
+                lds_read<H>(b_at(s + 1), bn);
             }
             if (s == PACK_AT) {
                 // Pack the panel fetched at the top of this iteration into the

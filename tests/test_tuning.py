@@ -128,3 +128,29 @@ def test_batched_validation_reports_the_bad_problem(native):
 def test_problem_struct_layout(native):
     # the C struct has natural alignment: char, char, pad, 3 x int64, 2 x float, 6 x (ptr/int64)
     assert ctypes.sizeof(native.mg_problem) == 8 + 24 + 8 + 48
+
+
+def test_split_plan_rules(native):
+    """Host-side split-K plan: ranges are multiples of 128 deep, K < 256 never
+    splits, forcing is validated, and the workspace covers the partials."""
+    try:
+        assert native.mg_force_splits(0, 4) == 0
+        assert native.mg_split_count(0, 64, 64, 1000) == 4      # ranges of 256
+        assert native.mg_split_count(0, 64, 64, 300) == 3       # ranges of 128
+        assert native.mg_split_count(0, 64, 64, 255) == 1       # too short to split
+        assert native.mg_split_count(3, 64, 64, 4096) == 1      # FP8 never splits
+        assert native.mg_gemm_workspace_size(0, "N", "N", 64, 66, 1000) == 4 * 64 * 68 * 4
+        assert native.mg_force_splits(0, 1) == 0
+        assert native.mg_split_count(0, 64, 64, 1000) == 1
+        assert native.mg_gemm_workspace_size(0, "N", "N", 64, 66, 1000) == 0
+        for bad in (0, -2, 17):
+            assert native.mg_force_splits(0, bad) == -101
+        assert native.mg_force_splits(7, 2) == -101
+    finally:
+        native.mg_force_splits(0, -1)
+    # automatic rule: a problem with enough tiles for every compute unit never splits
+    assert native.mg_split_count(0, 8192, 8192, 8192) == 1
+    assert native.mg_gemm_workspace_size(0, "N", "N", 8192, 8192, 8192) == 0
+    # one tile and a long K splits into ranges at least 256 deep
+    s = native.mg_split_count(0, 64, 64, 4096)
+    assert 2 <= s <= 16 and 4096 / s >= 256 - 128
