@@ -34,7 +34,8 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
 M = N = K = 8192
 ALPHA, BETA = 1.5, 0.5
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sgemm_f32_8192_nn_traffic.md")
-KERNEL_SOURCES = ["paper_2305_18236_amd/csrc/gemm_f32.hip", "paper_2305_18236_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_2305_18236_amd/csrc/gemm_f32.hip", "paper_2305_18236_amd/csrc/tile_f32.h",
+                  "paper_2305_18236_amd/csrc/common.h"]
 
 
 def kernel_source_hash() -> str:
