@@ -135,9 +135,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep"], default="sgemm",
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling"],
+                    default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
-                         "chain: forward + backward of Y = (X W1) W2")
+                         "chain: forward + backward of Y = (X W1) W2; fp8: FP8 path at 8192^3; "
+                         "sweep: FP32 shapes x layouts; tiling: Tiling vs Tiling+Packing over sizes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -169,6 +171,8 @@ def main():
         return bench_fp8(args, torch, si, native, dev)
     if args.workload == "sweep":
         return bench_sweep(args, torch, si, native, dev)
+    if args.workload == "tiling":
+        return bench_tiling(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -457,6 +461,61 @@ def bench_sweep(args, torch, si, native, dev):
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "sgemm_sweep", "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+TILING_SIZES = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
+
+
+def bench_tiling(args, torch, si, native, dev):
+    """The packing ablation of the paper's Section 4.1.2 on the FP32 path:
+    square SGEMMs C = A B (NN, alpha 1, beta 0) over the paper's sizes, each
+    timed with every tile configuration; "Tiling" is the best configuration
+    that loads operands straight into registers, "Tiling+Packing" the best one
+    that packs them into LDS (split-K allowed for both, as the library would
+    run them).  One JSON line with a row per size."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    ncfg = native.mg_num_configs(0)
+    rows = []
+    for n in TILING_SIZES:
+        A = torch.from_numpy(si.uniform((n * n,), si.seed_for(2, "A"))).to(dev)
+        B = torch.from_numpy(si.uniform((n * n,), si.seed_for(2, "B"))).to(dev)
+        C = torch.zeros(n * n, device=dev)
+        steps = max(args.steps, 200 if n <= 512 else 20)
+        per_cfg = {}
+        for cfg in range(ncfg):
+            native.check(native.mg_force_config(0, cfg), "mg_force_config")
+            try:
+                need = native.mg_gemm_workspace_size(0, "N", "N", n, n, n)
+                ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+                def run():
+                    native.check(native.mg_gemm(0, "N", "N", n, n, n, 1.0, A.data_ptr(), n, B.data_ptr(), n, 0.0,
+                                                C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+
+                per_cfg[cfg] = _time_ms(run, steps, args.warmup, torch, stream)
+            finally:
+                native.mg_force_config(0, -1)
+        flops = 2.0 * n ** 3
+        best = {}
+        for name, packs in (("tiling", 0), ("tiling_packing", 1)):
+            cands = {c: t for c, t in per_cfg.items() if native.mg_config_packs(0, c) == packs}
+            c = min(cands, key=cands.get)
+            best[name] = {"config": c, "us": round(cands[c] * 1e3, 2),
+                          "tflops": round(flops / (cands[c] * 1e-3) / 1e12, 3)}
+        rows.append({"M": n, "N": n, "K": n, **best,
+                     "packing_speedup": round(best["tiling"]["us"] / best["tiling_packing"]["us"], 3),
+                     "auto_config": native.mg_tuned_config(0, n, n, n)})
+        del A, B, C
+    big = rows[-1]
+    out = {"metric": "FP32 SGEMM time, Tiling vs Tiling+Packing over sizes", "unit": "TFLOP/s",
+           "value": big["tiling_packing"]["tflops"], "ms_per_step": big["tiling_packing"]["us"] / 1e3,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sgemm_packing_ablation", "alpha": 1.0, "beta": 0.0, "layout": "NN",
+                      "inputs": "uniform[-1,1]", "timing": "mean of back-to-back launches (HIP events)"},
            "rows": rows}
     print(json.dumps(out), flush=True)
 

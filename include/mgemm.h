@@ -127,6 +127,15 @@ int mg_num_configs(int path);
 int mg_config_info(int path, int index, int *out6);
 
 /*
+ * 1 if configuration `index` of `path` packs its operand panels into LDS
+ * before the micro-kernel reads them (the paper's Tiling+Packing strategy,
+ * Section 4.1.2), 0 if its lanes load operands straight from global memory
+ * into registers (the Tiling strategy: tiled loops, no packing), or
+ * MG_ERR_UNSUPPORTED for an unknown (path, index).
+ */
+int mg_config_packs(int path, int index);
+
+/*
  * Force the configuration used for `path` (id from mg_config_info), or -1 to
  * return to automatic selection.  Process-wide; meant for the autotuner.
  */

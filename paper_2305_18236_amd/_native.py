@@ -54,6 +54,8 @@ def lib():
     L.mg_config_info.restype = ci
     L.mg_force_config.argtypes = [ci, ci]
     L.mg_force_config.restype = ci
+    L.mg_config_packs.argtypes = [ci, ci]
+    L.mg_config_packs.restype = ci
     L.mg_force_splits.argtypes = [ci, ci]
     L.mg_force_splits.restype = ci
     L.mg_split_count.argtypes = [ci, i64, i64, i64]
@@ -181,6 +183,10 @@ def mg_config_info(path, index):
 
 def mg_force_config(path, config_id) -> int:
     return int(lib().mg_force_config(int(path), int(config_id)))
+
+
+def mg_config_packs(path, index) -> int:
+    return int(lib().mg_config_packs(int(path), int(index)))
 
 
 def mg_force_splits(path, splits) -> int:

@@ -44,6 +44,10 @@ const SgemmConfig kSgemmConfigs[] = {
     {5, 256, 256, 16, 128, 64},
     {6, 256, 256, 32, 128, 64},
     {7, 256, 256, 32, 128, 128},
+    // no packing ("Tiling"): operands loaded straight into registers, BK is
+    // the K chunk of one register fetch (tile_direct.h)
+    {8, 64, 64, 8, 32, 32, 1},
+    {9, 128, 128, 8, 64, 64, 1},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -58,6 +62,8 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 5: return launch_sgemm_cfg<256, 256, 16, 128, 64>(ta, tb, g, stream);
     case 6: return launch_sgemm_cfg<256, 256, 32, 128, 64>(ta, tb, g, stream);
     case 7: return launch_sgemm_cfg<256, 256, 32, 128, 128>(ta, tb, g, stream);
+    case 8:
+    case 9: return launch_sgemm_direct(cfg, ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -11,12 +11,14 @@ namespace mg {
 
 struct SgemmConfig {
     int id, bm, bn, bk, wm, wn;
+    int direct;   // 1: operands loaded straight into registers (no LDS packing)
 };
 
 extern const SgemmConfig kSgemmConfigs[];
 extern const int kNumSgemmConfigs;
 
 hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
+hipError_t launch_sgemm_direct(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
 extern const SgemmConfig kBf16Configs[];
 extern const int kNumBf16Configs;
 

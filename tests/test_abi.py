@@ -86,6 +86,9 @@ def test_config_registry(native):
         assert c["bk"] % 2 == 0
         # LDS budget of a double-buffered FP32 panel pair (160 KiB per CU on gfx950)
         assert 2 * (c["bm"] + c["bn"]) * c["bk"] * 4 <= 160 * 1024
+    packs = [native.mg_config_packs(0, i) for i in range(n)]
+    assert set(packs) == {0, 1} and packs[:8] == [1] * 8
+    assert native.mg_config_packs(0, n) == -101 and native.mg_config_packs(1, 0) == 1
     assert native.mg_force_config(0, n) == -101
     assert native.mg_force_config(9, 0) == -101
     assert native.mg_force_config(0, -1) == 0

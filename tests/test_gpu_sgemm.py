@@ -55,10 +55,11 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
-    """Each tile configuration over several tiles and a ragged tail."""
+    """Each tile configuration (8 and 9 without packing) over several tiles
+    and a ragged tail."""
     p = Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg * 4 + ord(tA) + ord(tB))
     _check(p, gpu, cfg=cfg)
 
@@ -152,3 +153,35 @@ def test_full_size_8192_sampled(gpu, tA, tB):
     err = oracle.normalized_error(C[I, J], cref, d)
     assert err <= TOL["fp32"], err
     assert np.isfinite(C).all()
+
+
+@pytest.mark.parametrize("cfg", [8, 9])
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 16), (33, 70, 13), (64, 64, 8), (130, 129, 100),
+                                   (5, 300, 3)])
+def test_unpacked_tiling_small_shapes(gpu, cfg, tA, tB, M, N, K):
+    """The no-packing configurations on the small shapes they are for: K not a
+    multiple of the 8-deep chunk, partial tiles in M and N."""
+    p = Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M * 3 + N * 5 + K + cfg)
+    _check(p, gpu, cfg=cfg)
+
+
+@pytest.mark.parametrize("cfg", [8, 9])
+def test_unpacked_tiling_unaligned_and_exact(gpu, cfg):
+    """Leading dimensions that rule out 16-byte loads, and integer inputs for
+    which the result is exact."""
+    p = Problem(70, 45, 37, "N", "T", 1.0, 0.5, seed=40 + cfg, lda=39, ldb=41, ldc=47)
+    _check(p, gpu, cfg=cfg)
+    q = Problem(150, 170, 200, "N", "N", 1.5, 0.5, seed=42 + cfg, dist="integers")
+    C, Cref, _ = _check(q, gpu, cfg=cfg)
+    assert np.array_equal(C, Cref)
+
+
+def test_packed_and_unpacked_agree(gpu):
+    """Tiling and Tiling+Packing compute the same product (up to rounding
+    order) on every layout."""
+    for tA, tB in LAYOUTS:
+        p = Problem(200, 180, 300, tA, tB, 1.0, 0.0, seed=44)
+        C8, Cref, _ = _check(p, gpu, cfg=8)
+        C0, _, _ = _check(p, gpu, cfg=0)
+        assert np.max(np.abs(C8 - C0)) <= 2e-5 * np.max(np.abs(Cref))
