@@ -135,11 +135,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling"],
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling", "engine"],
                     default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
                          "chain: forward + backward of Y = (X W1) W2; fp8: FP8 path at 8192^3; "
-                         "sweep: FP32 shapes x layouts; tiling: Tiling vs Tiling+Packing over sizes")
+                         "sweep: FP32 shapes x layouts; tiling: Tiling vs Tiling+Packing over sizes; "
+                         "engine: vector-ALU vs matrix-core micro-kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -173,6 +174,8 @@ def main():
         return bench_sweep(args, torch, si, native, dev)
     if args.workload == "tiling":
         return bench_tiling(args, torch, si, native, dev)
+    if args.workload == "engine":
+        return bench_engine(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -516,6 +519,72 @@ def bench_tiling(args, torch, si, native, dev):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "sgemm_packing_ablation", "alpha": 1.0, "beta": 0.0, "layout": "NN",
                       "inputs": "uniform[-1,1]", "timing": "mean of back-to-back launches (HIP events)"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+ENGINE_SIZES = [1024, 2048, 4096, 8192]
+# FP32 on the vector ALUs: the published 157.3 TFLOP/s (256 flop per clock per
+# CU at 2.4 GHz).  The kernels issue scalar v_fmac_f32 only (packed FP32 is
+# disabled at build time); they measure above 78.6 TFLOP/s, so scalar FMAs are
+# not limited to half the vector rate on this chip and the full figure is the
+# bound.
+VALU_FP32_PEAK = 256 * 256 * 2.4e9 / 1e12
+
+
+def bench_engine(args, torch, si, native, dev):
+    """The paper's generic-vs-MMA lowering comparison (Section 4.3) on the GPU:
+    the same packed macro level with the vector-ALU FMA micro-kernel and with
+    the MFMA micro-kernel, square FP32 SGEMMs (NN, alpha 1.5, beta 0.5).  MFMA
+    runs the automatic configuration; VALU the best of its configurations."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    ncfg = native.mg_num_configs(0)
+    valu_cfgs = [c for c in range(ncfg) if native.mg_config_uses_mfma(0, c) == 0]
+    rows = []
+    for n in ENGINE_SIZES:
+        A = torch.from_numpy(si.uniform((n * n,), si.seed_for(2, "A"))).to(dev)
+        B = torch.from_numpy(si.uniform((n * n,), si.seed_for(2, "B"))).to(dev)
+        C = torch.from_numpy(si.uniform((n * n,), si.seed_for(2, "C"))).to(dev)
+        steps = args.steps if n >= 4096 else max(args.steps, 50)
+
+        def timed(cfg):
+            if cfg is not None:
+                native.check(native.mg_force_config(0, cfg), "mg_force_config")
+            try:
+                need = native.mg_gemm_workspace_size(0, "N", "N", n, n, n)
+                ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+                def run():
+                    native.check(native.mg_gemm(0, "N", "N", n, n, n, ALPHA, A.data_ptr(), n, B.data_ptr(), n, BETA,
+                                                C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+
+                return _time_ms(run, steps, args.warmup, torch, stream)
+            finally:
+                native.mg_force_config(0, -1)
+
+        valu = {c: timed(c) for c in valu_cfgs}
+        vc = min(valu, key=valu.get)
+        mfma_ms = timed(None)
+        flops = 2.0 * n ** 3
+        tf_v, tf_m = flops / (valu[vc] * 1e-3) / 1e12, flops / (mfma_ms * 1e-3) / 1e12
+        rows.append({"M": n, "N": n, "K": n,
+                     "valu": {"config": vc, "ms": round(valu[vc], 4), "tflops": round(tf_v, 2),
+                              "frac_of_valu_peak": round(tf_v / VALU_FP32_PEAK, 3)},
+                     "mfma": {"config": native.mg_tuned_config(0, n, n, n), "ms": round(mfma_ms, 4),
+                              "tflops": round(tf_m, 2), "frac_of_mfma_peak": round(tf_m / PEAK_TFLOPS["fp32"], 3)},
+                     "mfma_speedup": round(valu[vc] / mfma_ms, 3)})
+        del A, B, C
+    big = rows[-1]
+    out = {"metric": "FP32 SGEMM TFLOP/s, vector-ALU vs matrix-core micro-kernel", "unit": "TFLOP/s",
+           "value": big["valu"]["tflops"], "ms_per_step": big["valu"]["ms"], "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sgemm_valu_vs_mfma", "alpha": ALPHA, "beta": BETA, "layout": "NN",
+                      "inputs": "uniform[-1,1]"},
+           "roofline": {"bound": "alu", "achieved": big["valu"]["tflops"], "peak": round(VALU_FP32_PEAK, 1),
+                        "unit": "TFLOP/s", "frac": big["valu"]["frac_of_valu_peak"], "traffic": None,
+                        "kernel": f"sgemm_valu_kernel (config {big['valu']['config']}) at 8192^3"},
            "rows": rows}
     print(json.dumps(out), flush=True)
 

@@ -136,6 +136,15 @@ int mg_config_info(int path, int index, int *out6);
 int mg_config_packs(int path, int index);
 
 /*
+ * 1 if configuration `index` of `path` runs its micro-kernel on the matrix
+ * cores (MFMA: the target-specific lowering of the paper's matrix-multiply
+ * intrinsic, Section 3.2), 0 if it runs it as scalar FP32 FMAs on the vector
+ * ALUs (the generic lowering), or MG_ERR_UNSUPPORTED for an unknown
+ * (path, index).
+ */
+int mg_config_uses_mfma(int path, int index);
+
+/*
  * Force the configuration used for `path` (id from mg_config_info), or -1 to
  * return to automatic selection.  Process-wide; meant for the autotuner.
  */

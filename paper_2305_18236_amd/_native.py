@@ -54,6 +54,8 @@ def lib():
     L.mg_config_info.restype = ci
     L.mg_force_config.argtypes = [ci, ci]
     L.mg_force_config.restype = ci
+    L.mg_config_uses_mfma.argtypes = [ci, ci]
+    L.mg_config_uses_mfma.restype = ci
     L.mg_config_packs.argtypes = [ci, ci]
     L.mg_config_packs.restype = ci
     L.mg_force_splits.argtypes = [ci, ci]
@@ -187,6 +189,10 @@ def mg_force_config(path, config_id) -> int:
 
 def mg_config_packs(path, index) -> int:
     return int(lib().mg_config_packs(int(path), int(index)))
+
+
+def mg_config_uses_mfma(path, index) -> int:
+    return int(lib().mg_config_uses_mfma(int(path), int(index)))
 
 
 def mg_force_splits(path, splits) -> int:

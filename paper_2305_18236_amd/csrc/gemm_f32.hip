@@ -48,6 +48,10 @@ const SgemmConfig kSgemmConfigs[] = {
     // the K chunk of one register fetch (tile_direct.h)
     {8, 64, 64, 8, 32, 32, 1},
     {9, 128, 128, 8, 64, 64, 1},
+    // vector-ALU micro-kernel (tile_valu.h): packed panels, 8 x 8 outputs per
+    // thread with scalar FP32 FMAs; WM x WN is one wave's share of the tile
+    {10, 128, 128, 8, 32, 128, 0, 1},
+    {11, 128, 128, 16, 32, 128, 0, 1},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -64,6 +68,8 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 7: return launch_sgemm_cfg<256, 256, 32, 128, 128>(ta, tb, g, stream);
     case 8:
     case 9: return launch_sgemm_direct(cfg, ta, tb, g, stream);
+    case 10:
+    case 11: return launch_sgemm_valu(cfg, ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -12,6 +12,7 @@ namespace mg {
 struct SgemmConfig {
     int id, bm, bn, bk, wm, wn;
     int direct;   // 1: operands loaded straight into registers (no LDS packing)
+    int valu;     // 1: vector-ALU FMA micro-kernel instead of the matrix cores
 };
 
 extern const SgemmConfig kSgemmConfigs[];
@@ -19,6 +20,7 @@ extern const int kNumSgemmConfigs;
 
 hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
 hipError_t launch_sgemm_direct(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
+hipError_t launch_sgemm_valu(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream);
 extern const SgemmConfig kBf16Configs[];
 extern const int kNumBf16Configs;
 

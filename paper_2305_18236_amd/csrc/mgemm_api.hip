@@ -516,6 +516,13 @@ int mg_config_packs(int path, int index)
     return t.cfgs[index].direct ? 0 : 1;
 }
 
+int mg_config_uses_mfma(int path, int index)
+{
+    const ConfigTable t = table_of(path);
+    if (index < 0 || index >= t.n) return MG_ERR_UNSUPPORTED;
+    return t.cfgs[index].valu ? 0 : 1;
+}
+
 int mg_force_config(int path, int config_id)
 {
     if (path < 0 || path > 3) return MG_ERR_UNSUPPORTED;

@@ -88,6 +88,9 @@ def test_config_registry(native):
         assert 2 * (c["bm"] + c["bn"]) * c["bk"] * 4 <= 160 * 1024
     packs = [native.mg_config_packs(0, i) for i in range(n)]
     assert set(packs) == {0, 1} and packs[:8] == [1] * 8
+    mfma = [native.mg_config_uses_mfma(0, i) for i in range(n)]
+    assert mfma[:10] == [1] * 10 and set(mfma[10:]) == {0}
+    assert native.mg_config_uses_mfma(0, n) == -101
     assert native.mg_config_packs(0, n) == -101 and native.mg_config_packs(1, 0) == 1
     assert native.mg_force_config(0, n) == -101
     assert native.mg_force_config(9, 0) == -101

@@ -55,11 +55,11 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
-    """Each tile configuration (8 and 9 without packing) over several tiles
-    and a ragged tail."""
+    """Each tile configuration over several tiles and a ragged tail (8 and 9
+    without packing, 10 and 11 with the vector-ALU micro-kernel)."""
     p = Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg * 4 + ord(tA) + ord(tB))
     _check(p, gpu, cfg=cfg)
 
@@ -185,3 +185,30 @@ def test_packed_and_unpacked_agree(gpu):
         C8, Cref, _ = _check(p, gpu, cfg=8)
         C0, _, _ = _check(p, gpu, cfg=0)
         assert np.max(np.abs(C8 - C0)) <= 2e-5 * np.max(np.abs(Cref))
+
+
+@pytest.mark.parametrize("cfg", [10, 11])
+def test_valu_microkernel_exact_and_unaligned(gpu, cfg):
+    """The vector-ALU micro-kernel: integer inputs give the exact result; odd
+    leading dimensions take the scalar load and store paths."""
+    q = Problem(257, 130, 300, "T", "N", 1.5, 0.5, seed=50 + cfg, dist="integers")
+    C, Cref, _ = _check(q, gpu, cfg=cfg)
+    assert np.array_equal(C, Cref)
+    p = Problem(70, 45, 33, "N", "T", 1.0, 0.5, seed=52 + cfg, lda=35, ldb=37, ldc=47)
+    _check(p, gpu, cfg=cfg)
+
+
+@pytest.mark.slow
+def test_valu_full_size_sampled(gpu):
+    """8192^3 on the vector-ALU micro-kernel, as the engine comparison runs it."""
+    nat = _native()
+    assert nat.mg_force_config(0, 10) == 0
+    try:
+        p = Problem(8192, 8192, 8192, "N", "N", 1.5, 0.5, seed=1001).to_device(gpu)
+        assert p.run() == 0
+        C = p.result()
+    finally:
+        nat.mg_force_config(0, -1)
+    I, J = si.sample_indices(8192, 8192, 2048, 97)
+    cref, d = p.oracle_entries(I, J)
+    assert oracle.normalized_error(C[I, J], cref, d) <= TOL["fp32"]
