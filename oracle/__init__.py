@@ -64,6 +64,14 @@ def _load():
     lib.oracle_tile_scale.argtypes = [dbl]
     lib.oracle_tile_scale.restype = dbl
     lib.oracle_fp8_quantize.argtypes = [i64, i64, ptr, i64, i64, ptr, ptr]
+    lib.oracle_fp16_round.argtypes = [i64, ptr, ptr]
+    i32 = ctypes.c_int32
+    lib.oracle_gemm_i8.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64, i32, ptr, i64, ptr, i64,
+                                   i32, ptr, i64, ptr, i64, ctypes.c_int]
+    lib.oracle_gemm_i8.restype = ctypes.c_int
+    lib.oracle_syr2k.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, dbl, ptr, i64, ptr, i64, dbl,
+                                 ptr, i64, ptr, ctypes.c_int]
+    lib.oracle_syr2k.restype = ctypes.c_int
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -187,6 +195,15 @@ def bf16_split(x):
     return hi, lo
 
 
+def fp16_round(x):
+    """Round each element to IEEE binary16, nearest-even, overflow to infinity
+    (Table 1's 16-bit floating operand type)."""
+    x64 = _f64(x)
+    out = np.empty_like(x64)
+    _load().oracle_fp16_round(x64.size, _p(x64), _p(out))
+    return out
+
+
 def e4m3_value(x: float) -> float:
     return float(_load().oracle_e4m3_value(float(x)))
 
@@ -268,3 +285,47 @@ def chain_grads(X, W1, W2, G, threads=None):
         "dX": gemm_logical(adH, np.abs(W1).T, threads=threads)[0],
     }
     return {"dX": dX, "dW1": dW1, "dW2": dW2}, den
+
+
+# ----------------------------------------------------------------- INT8 ----
+
+def gemm_i8(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta=0, C0=None, ldc0=None, threads=None):
+    """Integer GEMM of Table 1's 8-bit operand type: int8 A and B stored as
+    for gemm (row strides lda, ldb), int32 alpha, beta and C0.  Returns the
+    M x N int32 result alpha*op(A)*op(B) + beta*C0, computed exactly and
+    wrapped modulo 2^32."""
+    A8 = np.ascontiguousarray(A, dtype=np.int8)
+    B8 = np.ascontiguousarray(B, dtype=np.int8)
+    C = np.zeros((max(M, 1), max(N, 1)), dtype=np.int32)
+    if C0 is None:
+        C0a = np.zeros(1, dtype=np.int32)
+        ldc0 = 1
+        if beta != 0:
+            raise ValueError("beta != 0 needs C0")
+    else:
+        C0a = np.ascontiguousarray(C0, dtype=np.int32)
+        ldc0 = N if ldc0 is None else ldc0
+    _load().oracle_gemm_i8(_tchar(transA), _tchar(transB), M, N, K, int(alpha), _p(A8), lda, _p(B8), ldb,
+                           int(beta), _p(C0a), ldc0, _p(C), max(N, 1), _threads(threads))
+    return C[:M, :N]
+
+
+# ---------------------------------------------------------------- SYR2K ----
+
+def syr2k(uplo, trans, N, K, alpha, A, lda, B, ldb, beta=0.0, C0=None, ldc=None, threads=None):
+    """The SYR2K of Section 5.1 on one triangle, FP64.  A and B are stored as
+    N x K (trans 'N') or K x N (trans 'T') with row strides lda, ldb; C0 is
+    N x N with row stride ldc (default N).  Returns (C, D): C is C0 with the
+    uplo triangle replaced by alpha*(X Y^T + Y X^T) + beta*C0 (the other
+    triangle copied from C0 untouched), D the error denominator on the
+    triangle (0 elsewhere)."""
+    ldc = max(N, 1) if ldc is None else ldc
+    if C0 is None:
+        C = np.zeros(max(N, 1) * ldc, dtype=np.float64)
+    else:
+        C = np.array(C0, dtype=np.float64).reshape(-1).copy()
+    D = np.zeros(max(N, 1) * max(N, 1), dtype=np.float64)
+    A64, B64 = _f64(A), _f64(B)
+    _load().oracle_syr2k(_tchar(uplo), _tchar(trans), N, K, float(alpha), _p(A64), lda, _p(B64), ldb,
+                         float(beta), _p(C), ldc, _p(D), _threads(threads))
+    return C, D.reshape(max(N, 1), max(N, 1))[:N, :N]

@@ -39,6 +39,28 @@
  *            amax <= 448*s (s = 1 for an all-zero tile), q = E4M3(x/s)
  *            saturated to +-448.
  *
+ *   fp16 round
+ *            IEEE binary16 round-to-nearest-even (11 significant bits, min
+ *            normal 2^-14, subnormals below); a result above the largest
+ *            finite value 65504 becomes infinity.  Table 1's 16-bit floating
+ *            operand type beside bfloat16.
+ *
+ *   int8 gemm
+ *            Table 1's 8-bit integer operands: C = alpha*op(A)*op(B) + beta*C0
+ *            with int8 A and B and int32 C, alpha and beta.  The products are
+ *            summed exactly (int64), and alpha*sum + beta*C0 is reduced
+ *            modulo 2^32 into the int32 range (two's-complement wrap-around),
+ *            the reading taken for integer overflow, which the paper does not
+ *            discuss.  Same BLAS quick returns as gemm.
+ *
+ *   syr2k    The paper's worked extension of the macro level to another BLAS
+ *            kernel (Section 5.1): one triangle of
+ *              C = alpha*A*B^T + alpha*B*A^T + beta*C   (trans 'N', A, B N x K)
+ *              C = alpha*A^T*B + alpha*B^T*A + beta*C   (trans 'T', A, B K x N)
+ *            C symmetric, only the lower (uplo 'L': i >= j) or upper ('U':
+ *            i <= j) triangle read and written, BLAS conventions otherwise.
+ *            Written as the two dot products of the definition per entry.
+ *
  * Build: gcc -O2 -fopenmp -fno-fast-math -ffp-contract=off -shared -fPIC.
  * With contraction off, every multiply and add is a separately rounded IEEE
  * FP64 operation, so results do not depend on the compiler or thread count.
@@ -182,6 +204,20 @@ void oracle_bf16_round(int64_t n, const double *x, double *out)
     for (int64_t t = 0; t < n; ++t) out[t] = to_bf16(x[t]);
 }
 
+/* binary16 round-to-nearest-even of a value held in a double; overflow -> inf. */
+static double to_fp16(double x)
+{
+    double r = oracle_round_to_bits(x, 11, -14);
+    if (isfinite(r) && fabs(r) > 65504.0) r = copysign(INFINITY, r);
+    return r;
+}
+
+/* binary16 rounding of each element. */
+void oracle_fp16_round(int64_t n, const double *x, double *out)
+{
+    for (int64_t t = 0; t < n; ++t) out[t] = to_fp16(x[t]);
+}
+
 /* ------------------------------------------------------------- FP8 E4M3 -- */
 
 /* OCP E4M3 ("fn"): 1 sign, 4 exponent (bias 7), 3 mantissa bits, max 448,
@@ -263,6 +299,95 @@ void oracle_fp8_quantize(int64_t rows, int64_t cols, const double *X, int64_t ld
                     q[i * cols + j] = oracle_e4m3_encode(oracle_e4m3_value(X[i * ldx + j] / s));
         }
     }
+}
+
+/* --------------------------------------------------------------- INT8 -- */
+
+/* Reduce an int64 modulo 2^32 into [-2^31, 2^31) (two's complement). */
+static int32_t wrap32(int64_t v)
+{
+    return (int32_t)(uint32_t)(uint64_t)v;
+}
+
+/*
+ * C[i][j] = wrap32(alpha * sum_k opA[i][k]*opB[k][j] + beta * C0[i][j]) for
+ * int8 A, B (stored as for gemm) and int32 C0 / C (row stride ldc).  The sum
+ * is exact in int64 for K < 2^49.  beta == 0: C0 not read; alpha == 0 or
+ * K == 0: C = wrap32(beta * C0).
+ */
+int oracle_gemm_i8(char transA, char transB, int64_t M, int64_t N, int64_t K, int32_t alpha,
+                   const int8_t *A, int64_t lda, const int8_t *B, int64_t ldb, int32_t beta,
+                   const int32_t *C0, int64_t ldc0, int32_t *C, int64_t ldc, int threads)
+{
+    int ta = is_trans(transA), tb = is_trans(transB);
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t acc = 0;
+            if (alpha != 0)
+                for (int64_t k = 0; k < K; ++k) {
+                    int64_t a = ta ? A[k * lda + i] : A[i * lda + k];
+                    int64_t b = tb ? B[j * ldb + k] : B[k * ldb + j];
+                    acc += a * b;
+                }
+            int64_t v = (int64_t)alpha * acc;
+            if (beta != 0) v += (int64_t)beta * C0[i * ldc0 + j];
+            C[i * ldc + j] = wrap32(v);
+        }
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------------- SYR2K -- */
+
+/*
+ * One triangle of C = alpha*(X*Y^T + Y*X^T) + beta*C in place (C row-major,
+ * N x N, row stride ldc), with X = A, Y = B as N x K matrices when trans is
+ * 'N' (element (i, k) at A[i*lda + k]) or as the transposes of the stored
+ * K x N matrices when trans is 'T' (element (i, k) at A[k*lda + i]).
+ * D (row stride N) receives the error denominator
+ *   |alpha| * sum_k (|x_ik||y_jk| + |y_ik||x_jk|) + |beta||c_ij|
+ * on the triangle.  Entries outside the triangle are not touched.
+ */
+int oracle_syr2k(char uplo, char trans, int64_t N, int64_t K, double alpha, const double *A,
+                 int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                 double *D, int threads)
+{
+    int lower = (uplo == 'L' || uplo == 'l');
+    int tr = is_trans(trans);
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t j0 = lower ? 0 : i, j1 = lower ? i + 1 : N;
+        for (int64_t j = j0; j < j1; ++j) {
+            double s1 = 0.0, s2 = 0.0, d = 0.0;
+            if (alpha != 0.0) {
+                for (int64_t k = 0; k < K; ++k) {
+                    double xi = tr ? A[k * lda + i] : A[i * lda + k];
+                    double yj = tr ? B[k * ldb + j] : B[j * ldb + k];
+                    s1 += xi * yj;
+                    d += fabs(xi) * fabs(yj);
+                }
+                for (int64_t k = 0; k < K; ++k) {
+                    double yi = tr ? B[k * ldb + i] : B[i * ldb + k];
+                    double xj = tr ? A[k * lda + j] : A[j * lda + k];
+                    s2 += yi * xj;
+                    d += fabs(yi) * fabs(xj);
+                }
+            }
+            double c = C[i * ldc + j];
+            double r = alpha * (s1 + s2);
+            double db = fabs(alpha) * d;
+            if (beta != 0.0) {
+                r += beta * c;
+                db += fabs(beta) * fabs(c);
+            }
+            C[i * ldc + j] = (alpha == 0.0 || K == 0) ? (beta != 0.0 ? beta * c : 0.0) : r;
+            if (D) D[i * N + j] = db;
+        }
+    }
+    return 0;
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }

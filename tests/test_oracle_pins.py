@@ -368,3 +368,173 @@ def test_chain_grads_shapes_and_denominators():
     assert g["dX"].shape == (8, 3) and g["dW1"].shape == (3, 6) and g["dW2"].shape == (6, 2)
     for k in g:
         assert np.all(np.abs(g[k]) <= den[k] * (1 + 1e-12))
+
+
+# ------------------------------------------------------------------ FP16 ----
+
+def test_fp16_round_matches_library_conversion():
+    """numpy's float64 -> float16 cast rounds to nearest even and overflows to
+    infinity: the oracle's rounding must agree on normals, subnormals, ties
+    and the overflow edge."""
+    rng = np.random.default_rng(140)
+    x = np.concatenate([si.uniform(20000, 141).astype(np.float64),
+                        si.log_uniform_signed(20000, 142, -9, 5).astype(np.float64),
+                        rng.uniform(-70000, 70000, 5000),
+                        np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, -65520.0, 2.0 ** -24, 2.0 ** -25,
+                                  3 * 2.0 ** -25, 2.0 ** -14, 1e-9])])
+    # exact ties: halfway between two adjacent binary16 values
+    h = rng.integers(0x0400, 0x7bff, 5000).astype(np.uint16).view(np.float16).astype(np.float64)
+    ulp = np.spacing(h.astype(np.float16)).astype(np.float64)
+    x = np.concatenate([x, h + ulp / 2, -(h + ulp / 2)])
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(oracle.fp16_round(x), ref)
+
+
+def test_fp16_round_by_hand():
+    r = oracle.fp16_round
+    assert r([1 / 3])[0] == 0.333251953125            # 0x3555
+    assert r([65504.0])[0] == 65504.0                 # largest finite
+    assert r([65519.99])[0] == 65504.0                # below the midpoint to 2^16
+    assert np.isinf(r([65520.0])[0])                  # the midpoint rounds to even: 2^16 -> inf
+    assert r([2.0 ** -24])[0] == 2.0 ** -24           # smallest subnormal
+    assert r([2.0 ** -25])[0] == 0.0                  # tie between 0 and 2^-24 -> even (0)
+    assert r([3 * 2.0 ** -25])[0] == 2.0 ** -23       # tie between 2^-24 and 2^-23 -> even (2^-23)
+    assert r([1 + 2.0 ** -11])[0] == 1.0              # tie -> even
+    assert r([1 + 3 * 2.0 ** -11])[0] == 1 + 2.0 ** -9
+
+
+# ------------------------------------------------------------------ INT8 ----
+
+def _wrap32(v: int) -> int:
+    return ((v + 2 ** 31) % 2 ** 32) - 2 ** 31
+
+
+@pytest.mark.parametrize("tA,tB", [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (3, 4, 5), (6, 2, 7), (5, 5, 0)])
+def test_gemm_i8_exact_vs_python_integers(tA, tB, M, N, K):
+    """Python's unbounded integers give the exact value; the wrap modulo 2^32
+    is applied by hand (large alpha and beta force it)."""
+    rng = np.random.default_rng(150 + M + N + K)
+    opA = rng.integers(-128, 128, (M, K)).astype(np.int8)
+    opB = rng.integers(-128, 128, (K, N)).astype(np.int8)
+    C0 = rng.integers(-2 ** 31, 2 ** 31, (M, N)).astype(np.int32)
+    for alpha, beta in [(1, 0), (-3, 2), (2 ** 30 - 7, -(2 ** 29) + 3), (0, 5)]:
+        A = opA if tA == "N" else np.ascontiguousarray(opA.T)
+        B = opB if tB == "N" else np.ascontiguousarray(opB.T)
+        lda = max(A.shape[1], 1)
+        ldb = max(B.shape[1], 1)
+        got = oracle.gemm_i8(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, N)
+        for i in range(M):
+            for j in range(N):
+                acc = sum(int(opA[i, k]) * int(opB[k, j]) for k in range(K))
+                want = _wrap32(alpha * acc + (beta * int(C0[i, j]) if beta else 0))
+                assert int(got[i, j]) == want
+
+
+def test_gemm_i8_matches_library_int64_matmul():
+    rng = np.random.default_rng(151)
+    opA = rng.integers(-128, 128, (64, 300)).astype(np.int8)
+    opB = rng.integers(-128, 128, (300, 48)).astype(np.int8)
+    got = oracle.gemm_i8("N", "N", 64, 48, 300, 1, opA, 300, opB, 48)
+    ref = opA.astype(np.int64) @ opB.astype(np.int64)
+    assert np.array_equal(got.astype(np.int64), ref)
+
+
+def test_gemm_i8_extremes_closed_form():
+    """All entries -128 at the largest K whose sums stay below 2^31:
+    every sum is K * 16384; doubling it wraps."""
+    K = 131071
+    A = np.full((2, K), -128, np.int8)
+    B = np.full((K, 3), -128, np.int8)
+    got = oracle.gemm_i8("N", "N", 2, 3, K, 1, A, K, B, 3)
+    assert np.all(got == K * 16384)
+    got2 = oracle.gemm_i8("N", "N", 2, 3, K, 2, A, K, B, 3)
+    assert np.all(got2 == 2 * K * 16384 - 2 ** 32)
+
+
+def test_gemm_i8_quick_returns():
+    A = np.ones((2, 3), np.int8)
+    B = np.ones((3, 2), np.int8)
+    C0 = np.array([[7, -9], [2 ** 31 - 1, 5]], np.int32)
+    # beta == 0: C0 is not read
+    assert np.array_equal(oracle.gemm_i8("N", "N", 2, 2, 3, 4, A, 3, B, 2, 0, C0, 2), np.full((2, 2), 12))
+    # alpha == 0: beta * C0, wrapped
+    got = oracle.gemm_i8("N", "N", 2, 2, 3, 0, A, 3, B, 2, 2, C0, 2)
+    assert np.array_equal(got, np.array([[14, -18], [-2, 10]]))
+
+
+# ----------------------------------------------------------------- SYR2K ----
+
+def _syr2k_inputs(N, K, trans, seed, dist=si.dyadic):
+    X = dist((N, K), seed)
+    Y = dist((N, K), seed + 1)
+    if trans == "N":
+        return X, Y, X.copy(), Y.copy(), K
+    return X, Y, np.ascontiguousarray(X.T), np.ascontiguousarray(Y.T), N
+
+
+@pytest.mark.parametrize("uplo", ["L", "U"])
+@pytest.mark.parametrize("trans", ["N", "T"])
+@pytest.mark.parametrize("N,K", [(1, 1), (3, 2), (4, 5), (5, 3)])
+def test_syr2k_exact_rational(uplo, trans, N, K):
+    """Dyadic inputs: exact rational arithmetic of the definition equals the
+    oracle exactly on the triangle, and the other triangle is untouched."""
+    X, Y, A, B, ld = _syr2k_inputs(N, K, trans, 160 + N + K)
+    C0 = si.dyadic((N, N), 170 + N)
+    alpha, beta = 1.5, -0.75
+    C, _ = oracle.syr2k(uplo, trans, N, K, alpha, A, ld, B, ld, beta, C0)
+    C = C.reshape(N, N)
+    for i in range(N):
+        for j in range(N):
+            inside = (i >= j) if uplo == "L" else (i <= j)
+            if not inside:
+                assert C[i, j] == C0[i, j]
+                continue
+            s = sum(Fraction(float(X[i, k])) * Fraction(float(Y[j, k])) +
+                    Fraction(float(Y[i, k])) * Fraction(float(X[j, k])) for k in range(K))
+            assert Fraction(C[i, j]) == Fraction(alpha) * s + Fraction(beta) * Fraction(float(C0[i, j]))
+
+
+def test_syr2k_matches_library_matmul():
+    N, K = 50, 30
+    X, Y = si.uniform((N, K), 180), si.uniform((N, K), 181)
+    C0 = si.uniform((N, N), 182)
+    C, D = oracle.syr2k("L", "N", N, K, -1.25, X, K, Y, K, 0.5, C0)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    ref = -1.25 * (X64 @ Y64.T + Y64 @ X64.T) + 0.5 * C0
+    low = np.tril_indices(N)
+    assert np.allclose(C.reshape(N, N)[low], ref[low], rtol=0, atol=1e-12)
+    dref = 1.25 * (np.abs(X64) @ np.abs(Y64).T + np.abs(Y64) @ np.abs(X64).T) + 0.5 * np.abs(C0)
+    assert np.allclose(D[low], dref[low], rtol=1e-13, atol=0)
+
+
+def test_syr2k_symmetries():
+    """Swapping A and B changes nothing; the upper triangle is the transpose
+    of the lower one when C0 is symmetric; beta == 0 never reads C."""
+    N, K = 23, 17
+    X, Y = si.uniform((N, K), 190), si.uniform((N, K), 191)
+    S = si.uniform((N, N), 192)
+    C0 = (S + S.T) / 2
+    L, _ = oracle.syr2k("L", "N", N, K, 0.7, X, K, Y, K, 0.3, C0)
+    L2, _ = oracle.syr2k("L", "N", N, K, 0.7, Y, K, X, K, 0.3, C0)
+    U, _ = oracle.syr2k("U", "N", N, K, 0.7, X, K, Y, K, 0.3, C0)
+    assert np.array_equal(L, L2)
+    L, U = L.reshape(N, N), U.reshape(N, N)
+    low = np.tril_indices(N)
+    assert np.array_equal(L[low], U.T[low])
+    Cn = np.full((N, N), np.nan)
+    Z, _ = oracle.syr2k("L", "N", N, K, 0.7, X, K, Y, K, 0.0, Cn)
+    assert not np.isnan(Z.reshape(N, N)[low]).any()
+
+
+def test_syr2k_equal_operands_closed_form():
+    """A == B (integers): C = 2*alpha*A*A^T + beta*C0, exactly."""
+    N, K = 31, 40
+    X = si.integers((N, K), 193)
+    C0 = si.integers((N, N), 194)
+    C, _ = oracle.syr2k("U", "N", N, K, 1.5, X, K, X, K, 0.5, C0)
+    Xi = X.astype(np.int64)
+    ref = 1.5 * 2 * (Xi @ Xi.T) + 0.5 * C0
+    up = np.triu_indices(N)
+    assert np.array_equal(C.reshape(N, N)[up], ref[up])
