@@ -68,7 +68,7 @@ def time_path(path, A, B, C, steps, warmup, torch, native):
     """Run `warmup` + `steps` GEMMs on the current stream; per-launch HIP events."""
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
-    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}[path]
     need = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
 
@@ -97,7 +97,7 @@ def time_path(path, A, B, C, steps, warmup, torch, native):
 def single_result(path, A, B, C0_dev, torch, native):
     """One GEMM from the original C0 (for the error check)."""
     C = C0_dev.clone()
-    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}[path]
     need = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
     st = native.mg_gemm(pid, "N", "N", M, N, K, ALPHA, A.data_ptr(), K, B.data_ptr(), N, BETA,
@@ -590,7 +590,7 @@ def bench_engine(args, torch, si, native, dev):
 
 
 def _path_supported(native, path) -> bool:
-    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}[path]
+    pid = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}[path]
     return native.mg_num_configs(pid) > 0
 
 

@@ -57,8 +57,10 @@ enum mg_path {
     MG_PATH_BF16X3 = 1,   /* x = hi + lo (bf16 each); hi*hi + hi*lo + lo*hi on
                              BF16 MFMA, FP32 accumulation                         */
     MG_PATH_BF16 = 2,     /* operands rounded to bf16 (nearest-even), FP32 acc.  */
-    MG_PATH_FP8_T128 = 3  /* OCP E4M3 with one power-of-two FP32 scale per
+    MG_PATH_FP8_T128 = 3, /* OCP E4M3 with one power-of-two FP32 scale per
                              128 x 128 tile of op(A) and op(B), FP32 accumulation */
+    MG_PATH_FP16 = 4      /* operands rounded to IEEE binary16 (nearest-even;
+                             |x| >= 65520 becomes infinity), FP32 accumulation */
 };
 
 enum mg_status {

@@ -12,7 +12,7 @@ import os
 from . import _native
 from ._native import MgemmError, check, status_string  # noqa: F401
 
-PATHS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+PATHS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}
 
 
 def _path_id(path) -> int:
@@ -52,7 +52,7 @@ def gemm(A, B, C=None, *, alpha: float = 1.0, beta: float = 0.0, path="fp32", wo
 
     A and B may be row-major or transposed views; C must be row-major
     (contiguous rows).  If C is None a new M x N tensor is returned (and beta
-    must be 0).  ``path`` is "fp32", "bf16x3", "bf16" or "fp8".
+    must be 0).  ``path`` is "fp32", "bf16x3", "bf16", "fp16" or "fp8".
     """
     import torch
     if A.dtype != torch.float32 or B.dtype != torch.float32:

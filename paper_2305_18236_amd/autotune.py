@@ -33,9 +33,9 @@ import time
 
 from . import _native
 
-PATH_IDS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+PATH_IDS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}
 SLOTS = 512          # workgroup slots of the persistent kernel: 256 CUs x 2
-BATCHED_CFGS = {0: [3, 0], 1: [4, 5, 2], 2: [4, 5, 2]}
+BATCHED_CFGS = {0: [3, 0], 1: [4, 5, 2], 2: [4, 5, 2], 4: [4, 5, 2]}
 
 
 def bucket(x: int) -> int:

@@ -95,6 +95,7 @@ static const void* batched_kernel(int path)
     case 0: return reinterpret_cast<const void*>(&sgemm_batched_kernel);
     case 1: return reinterpret_cast<const void*>(&bf16_batched_kernel<3>);
     case 2: return reinterpret_cast<const void*>(&bf16_batched_kernel<1>);
+    case 4: return reinterpret_cast<const void*>(&bf16_batched_kernel<16>);
     default: return nullptr;
     }
 }
@@ -116,6 +117,7 @@ hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int c
     case 0: hipLaunchKernelGGL(sgemm_batched_kernel, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
     case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
     case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
+    case 4: hipLaunchKernelGGL(bf16_batched_kernel<16>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

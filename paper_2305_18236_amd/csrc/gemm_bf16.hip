@@ -73,14 +73,19 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
 
 hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream, bool packed)
 {
-    return terms == 3 ? launch_terms<3>(cfg, ta, tb, g, stream, packed)
-                      : launch_terms<1>(cfg, ta, tb, g, stream, packed);
+    switch (terms) {
+    case 1: return launch_terms<1>(cfg, ta, tb, g, stream, packed);
+    case 3: return launch_terms<3>(cfg, ta, tb, g, stream, packed);
+    case 16: return launch_terms<16>(cfg, ta, tb, g, stream, packed);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Pre-pack of one operand for the BF16 paths: the logical R x Kd matrix
-// op(X) (stored R x Kd when T is false, Kd x R when true) is rounded (TERMS 1)
-// or split into hi/lo (TERMS 3) once and written as k-contiguous bf16 rows
+// op(X) (stored R x Kd when T is false, Kd x R when true) is rounded (TERMS 1:
+// bf16, 16: fp16) or split into hi/lo (TERMS 3) once and written as
+// k-contiguous 16-bit rows
 // hi[Rp][ldq] (and lo[Rp][ldq]), zero outside R x Kd.  One workgroup of 256
 // threads per 128 x 128 tile; the tile goes through LDS so that both stored
 // layouts write whole 16-byte row chunks.
@@ -119,8 +124,8 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict_
         const int id = tid + 256 * s;
         const int sr = id / 32, scol = 4 * (id % 32);
         uint32_t h[2], l[2];
-        if (TERMS == 3) split4(v[s], h, l);
-        else round4(v[s], h);
+        if constexpr (TERMS == 3) split4(v[s], h, l);
+        else convert4<TERMS>(v[s], h);
         if (!T) {
             // stored row = logical row, columns = k .. k+3
             *reinterpret_cast<uint2*>(&th[sr * PROW + scol]) = make_uint2(h[0], h[1]);
@@ -150,12 +155,20 @@ hipError_t launch_bf16_pack(bool trans, int terms, const float* X, int64_t ldx, 
                             hipStream_t stream)
 {
     const dim3 grid(unsigned(Kp / PT), unsigned(Rp / PT)), block(256);
-    if (terms == 3) {
+    switch (terms) {
+    case 3:
         if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 3>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
         else hipLaunchKernelGGL((bf16_pack_kernel<false, 3>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
-    } else {
+        break;
+    case 1:
         if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 1>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
         else hipLaunchKernelGGL((bf16_pack_kernel<false, 1>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+        break;
+    case 16:
+        if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 16>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+        else hipLaunchKernelGGL((bf16_pack_kernel<false, 16>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);
+        break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -18,8 +18,18 @@ namespace {
 bool is_n(char t) { return t == 'N' || t == 'n'; }
 bool is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 
-std::atomic<int> g_forced[4] = {{-1}, {-1}, {-1}, {-1}};
-std::atomic<int> g_forced_splits[4] = {{-1}, {-1}, {-1}, {-1}};
+constexpr int kPaths = 5;
+std::atomic<int> g_forced[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_forced_splits[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}};
+
+bool valid_path(int path) { return path >= 0 && path < kPaths; }
+
+// Paths the 16-bit matrix-core kernels run, and their TERMS kind.
+bool is_16bit(int path) { return path == MG_PATH_BF16X3 || path == MG_PATH_BF16 || path == MG_PATH_FP16; }
+int kind_of(int path) { return path == MG_PATH_BF16X3 ? 3 : path == MG_PATH_FP16 ? 16 : 1; }
+
+// Paths the persistent batched kernel runs.
+bool batched_path(int path) { return valid_path(path) && path != MG_PATH_FP8_T128; }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP - int(e); }
 
@@ -65,7 +75,8 @@ ConfigTable table_of(int path)
     switch (path) {
     case MG_PATH_FP32: return {mg::kSgemmConfigs, mg::kNumSgemmConfigs};
     case MG_PATH_BF16X3:
-    case MG_PATH_BF16: return {mg::kBf16Configs, mg::kNumBf16Configs};
+    case MG_PATH_BF16:
+    case MG_PATH_FP16: return {mg::kBf16Configs, mg::kNumBf16Configs};
     case MG_PATH_FP8_T128: return {mg::kFp8Configs, mg::kNumFp8Configs};
     default: return {nullptr, 0};
     }
@@ -76,7 +87,7 @@ ConfigTable table_of(int path)
 // GEMMs, mode 1 ('b') by the batched kernel (which falls back to mode 0).
 // bucket(x) = round(log2 x), clamped to [0, kBuckets).  -1: not tuned.
 constexpr int kBuckets = 21;
-int8_t g_table[2][4][kBuckets][kBuckets][kBuckets];
+int8_t g_table[2][kPaths][kBuckets][kBuckets][kBuckets];
 std::once_flag g_table_init;
 std::mutex g_table_mutex;
 
@@ -133,7 +144,8 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         if (tiles(M, N, 128, 128) >= 128) return 2;
         return 3;
     }
-    if (path == MG_PATH_BF16 && tiles(M, N, 128, 128) >= 1024) return 2;   // pre-packed: 128 x 128 best
+    if ((path == MG_PATH_BF16 || path == MG_PATH_FP16) && tiles(M, N, 128, 128) >= 1024)
+        return 2;   // pre-packed: 128 x 128 best
     // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the
     // paper finds for small matrices (measured: 0.84x the packed time at 16^3,
     // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
@@ -187,7 +199,7 @@ Fp8Workspace fp8_workspace(int64_t M, int64_t N, int64_t K)
 // bf16x3 converts in the kernel.
 bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 {
-    return path == MG_PATH_BF16 && M >= 512 && N >= 512 && K >= 32;
+    return (path == MG_PATH_BF16 || path == MG_PATH_FP16) && M >= 512 && N >= 512 && K >= 32;
 }
 
 struct Bf16Workspace {
@@ -299,8 +311,9 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     switch (path) {
     case MG_PATH_FP32: return finish(mg::launch_sgemm(cfg, ta, tb, g, stream));
     case MG_PATH_BF16X3:
-    case MG_PATH_BF16: {
-        const int terms = path == MG_PATH_BF16X3 ? 3 : 1;
+    case MG_PATH_BF16:
+    case MG_PATH_FP16: {
+        const int terms = kind_of(path);
         if (bf16_planes == nullptr) return finish(mg::launch_gemm_bf16(terms, cfg, ta, tb, g, stream));
         // pack each operand once, then multiply the packed planes
         const Bf16Workspace w = bf16_workspace(path, M, N, K);
@@ -413,7 +426,7 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     size_t left = (ws != nullptr && (reinterpret_cast<uintptr_t>(ws) & 255) == 0) ? workspace_bytes : 0;
     void* planes = nullptr;
-    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K)) {
+    if (is_16bit(path) && bf16_prepack_pays(path, M, N, K)) {
         const size_t need = align256(bf16_workspace(path, M, N, K).total);
         if (left >= need) {
             planes = ws;
@@ -440,7 +453,7 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int
     if (M <= 0 || N <= 0 || K <= 0 || table_of(path).n == 0) return 0;
     if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
     size_t total = 0;
-    if ((path == MG_PATH_BF16X3 || path == MG_PATH_BF16) && bf16_prepack_pays(path, M, N, K))
+    if (is_16bit(path) && bf16_prepack_pays(path, M, N, K))
         total += align256(bf16_workspace(path, M, N, K).total);
     total += split_plan(path, pick_config(path, M, N, K), M, N, K).bytes;
     return total;
@@ -525,7 +538,7 @@ int mg_config_uses_mfma(int path, int index)
 
 int mg_force_config(int path, int config_id)
 {
-    if (path < 0 || path > 3) return MG_ERR_UNSUPPORTED;
+    if (!valid_path(path)) return MG_ERR_UNSUPPORTED;
     if (config_id < -1 || config_id >= mg_num_configs(path)) return MG_ERR_UNSUPPORTED;
     g_forced[path].store(config_id);
     return MG_OK;
@@ -533,7 +546,7 @@ int mg_force_config(int path, int config_id)
 
 int mg_force_splits(int path, int splits)
 {
-    if (path < 0 || path > 3) return MG_ERR_UNSUPPORTED;
+    if (!valid_path(path)) return MG_ERR_UNSUPPORTED;
     if (splits < -1 || splits == 0 || splits > kMaxSplits) return MG_ERR_UNSUPPORTED;
     g_forced_splits[path].store(splits);
     return MG_OK;
@@ -564,7 +577,7 @@ int mg_load_tuning(const char* path)
     }
     FILE* f = std::fopen(path, "r");
     if (!f) return MG_ERR_BAD_TABLE;
-    static int8_t fresh[2][4][kBuckets][kBuckets][kBuckets];
+    static int8_t fresh[2][kPaths][kBuckets][kBuckets][kBuckets];
     std::memset(fresh, -1, sizeof(fresh));
     char line[256];
     int bad = 0;
@@ -575,7 +588,7 @@ int mg_load_tuning(const char* path)
         int p, mb, nb, kb, cfg;
         char mode[8] = "s";
         const int got = std::sscanf(q, "%d %d %d %d %d %7s", &p, &mb, &nb, &kb, &cfg, mode);
-        if (got < 5 || p < 0 || p > 3 || mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 ||
+        if (got < 5 || !valid_path(p) || mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 ||
             kb >= kBuckets || cfg < 0 || cfg >= table_of(p).n || !(mode[0] == 's' || mode[0] == 'b') ||
             mode[1] != 0) {
             bad = 1;
@@ -591,26 +604,26 @@ int mg_load_tuning(const char* path)
 
 int mg_tuned_config(int path, int64_t M, int64_t N, int64_t K)
 {
-    if (path < 0 || path > 3 || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    if (!valid_path(path) || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
     return pick_config(path, M, N, K);
 }
 
 int mg_batched_config(int path, int64_t M, int64_t N, int64_t K)
 {
-    if (path < 0 || path > 2 || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    if (!batched_path(path) || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
     return batched_cfgs(path)[choose_batched_variant(path, M, N, K)];
 }
 
 size_t mg_gemm_batched_workspace_size(int path, int64_t count)
 {
-    if (path < 0 || path > 2) return 0;
+    if (!batched_path(path)) return 0;
     return batched_workspace(count);
 }
 
 int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* workspace,
                     size_t workspace_bytes, void* stream, int64_t* bad_problem)
 {
-    if (path < 0 || path > 2) return MG_ERR_UNSUPPORTED;
+    if (!batched_path(path)) return MG_ERR_UNSUPPORTED;
     if (count < 0) return -2;
     if (count > INT_MAX) return MG_ERR_TOO_LARGE;
     if (count > 0 && problems == nullptr) return -3;

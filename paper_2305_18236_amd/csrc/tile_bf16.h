@@ -1,6 +1,7 @@
 #pragma once
-// GEMM on the BF16 matrix cores of gfx950 (v_mfma_f32_32x32x16_bf16) with FP32
-// inputs, outputs and accumulation.  Two arithmetic variants:
+// GEMM on the 16-bit matrix cores of gfx950 (v_mfma_f32_32x32x16_bf16 and
+// v_mfma_f32_32x32x16_f16) with FP32 inputs, outputs and accumulation.  The
+// TERMS parameter selects the arithmetic:
 //
 //   TERMS == 1  (plain BF16): each operand is rounded to bfloat16 (nearest,
 //               ties to even) while it is packed into LDS.
@@ -8,6 +9,10 @@
 //               hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32),
 //               and the micro-kernel accumulates hi*hi + hi*lo + lo*hi in FP32;
 //               the dropped lo*lo term is below 2^-16 |a||b|.
+//   TERMS == 16 (FP16): each operand is rounded to IEEE binary16 (nearest,
+//               ties to even; beyond 65504 it overflows to infinity) and the
+//               FP16 matrix instruction multiplies them (Table 1's 16-bit
+//               float row, like BF16).
 //
 // Layers follow Algorithm 1 of Kuzma et al. (SPE 2023) as in the FP32 kernel
 // (workgroup tiles for the i/j block loops, an in-kernel K-panel loop, packing
@@ -54,6 +59,40 @@ MG_DEVICE void round4(floatx4 x, uint32_t (&hi)[2])
 {
     hi[0] = pack_bf16x2(x[0], x[1]);
     hi[1] = pack_bf16x2(x[2], x[3]);
+}
+
+// Round two floats to binary16 (hardware RNE) and return them packed.
+MG_DEVICE uint32_t pack_f16x2(float a, float b)
+{
+    typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+    f16x2_t v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// The single-term conversion of kind TERMS (1: bf16, 16: fp16).
+template <int TERMS>
+MG_DEVICE void convert4(floatx4 x, uint32_t (&hi)[2])
+{
+    if constexpr (TERMS == 16) {
+        hi[0] = pack_f16x2(x[0], x[1]);
+        hi[1] = pack_f16x2(x[2], x[3]);
+    } else {
+        round4(x, hi);
+    }
+}
+
+// One rank-16 update of a 32 x 32 FP32 accumulator by the 16-bit matrix
+// instruction of kind TERMS (both operands hold eight 16-bit values per lane).
+template <int TERMS>
+MG_DEVICE floatx16 mfma16(bf16x8 a, bf16x8 b, floatx16 c)
+{
+    if constexpr (TERMS == 16) {
+        typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b),
+                                                      c, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
 }
 
 // One operand panel: ROWS (m or n) x BK (k), FP32 in global memory, packed
@@ -167,11 +206,11 @@ struct BfPanel {
     MG_DEVICE static void put(uint16_t* hi_lds, uint16_t* lo_lds, int off, floatx4 x)
     {
         uint32_t h[2], l[2];
-        if (TERMS == 3) {
+        if constexpr (TERMS == 3) {
             split4(x, h, l);
             *reinterpret_cast<uint2*>(lo_lds + off) = make_uint2(l[0], l[1]);
         } else {
-            round4(x, h);
+            convert4<TERMS>(x, h);
         }
         *reinterpret_cast<uint2*>(hi_lds + off) = make_uint2(h[0], h[1]);
     }
@@ -336,18 +375,18 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
                 for (int i = 0; i < V; ++i)
 #pragma unroll
                     for (int j = 0; j < H; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = mfma16<TERMS>(al[i], bh[j], acc[i][j]);
 #pragma unroll
                 for (int i = 0; i < V; ++i)
 #pragma unroll
                     for (int j = 0; j < H; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = mfma16<TERMS>(ah[i], bl[j], acc[i][j]);
             }
 #pragma unroll
             for (int i = 0; i < V; ++i)
 #pragma unroll
                 for (int j = 0; j < H; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = mfma16<TERMS>(ah[i], bh[j], acc[i][j]);
         }
         // Keep the pack (which waits for this iteration's global loads) after
         // the MFMAs: the compiler may otherwise hoist the LDS writes above

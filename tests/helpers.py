@@ -8,7 +8,7 @@ import numpy as np
 import oracle
 import seeded_inputs as si
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp8": 6e-2}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp8": 6e-2, "fp16": 2e-3}
 
 # bf16x3 leaves a per-product error of at most about 3 * 2^-16 |a||b| (the
 # dropped lo*lo term and the two split residuals, each <= 2^-16).  The 1e-5
@@ -23,7 +23,7 @@ def tolerance(path: str, K: int) -> float:
     return TOL[path]
 
 
-PATH_ID = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3}
+PATH_ID = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}
 
 
 def device_buffer(host_1d: np.ndarray, torch_device):

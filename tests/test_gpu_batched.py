@@ -14,7 +14,7 @@ from helpers import Problem, tolerance
 pytestmark = pytest.mark.gpu
 
 PATHS = ["fp32", "bf16x3", "bf16"]
-PID = {"fp32": 0, "bf16x3": 1, "bf16": 2}
+PID = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp16": 4}
 
 
 def _run_batched(probs, path, dev):
