@@ -63,6 +63,11 @@ enum mg_path {
                              |x| >= 65520 becomes infinity), FP32 accumulation */
 };
 
+/* Configuration table of the INT8 entry points (mg_gemm_i8, mg_gemm_i8_packed)
+ * for mg_num_configs, mg_config_info, mg_force_config and mg_tuned_config.
+ * Not a path of mg_gemm: its operands are int8, not FP32. */
+enum { MG_CONFIGS_I8 = 5 };
+
 enum mg_status {
     MG_OK = 0,
     MG_ERR_WORKSPACE = -100,    /* workspace missing or smaller than required */
@@ -117,6 +122,38 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
  * state (forced configuration, tuning table, forced split; 0 when none). */
 size_t mg_gemm_workspace_size(int path, char transA, char transB,
                               int64_t M, int64_t N, int64_t K);
+
+/*
+ * INT8 GEMM, the 8-bit integer operand type of the paper's Table 1:
+ *   C <- alpha * op(A) * op(B) + beta * C
+ * with int8 A and B (device pointers, stored and strided exactly as for
+ * mg_sgemm, same argument codes), int32 C, alpha and beta.  The products are
+ * summed exactly in int32 (K <= 131071 keeps every partial sum in range; a
+ * larger K returns MG_ERR_TOO_LARGE), and alpha*sum + beta*C is computed
+ * modulo 2^32 (two's-complement wrap-around).  beta == 0: C is not read;
+ * alpha == 0 or K == 0: C <- beta*C.  `workspace` (device, caller-owned,
+ * 256-byte aligned, mg_gemm_i8_workspace_size() bytes) receives the packed
+ * operands (MG_ERR_WORKSPACE if missing or too small when a product is formed).
+ */
+int mg_gemm_i8(char transA, char transB, int64_t M, int64_t N, int64_t K,
+               int32_t alpha, const int8_t *A, int64_t lda, const int8_t *B, int64_t ldb,
+               int32_t beta, int32_t *C, int64_t ldc,
+               void *workspace, size_t workspace_bytes, void *stream);
+size_t mg_gemm_i8_workspace_size(int64_t M, int64_t N, int64_t K);
+
+/*
+ * The INT8 pack stage on its own, for operands packed once and reused.
+ * mg_i8_pack writes op(X) (R x K; stored R x K when trans is 'N', K x R when
+ * 'T', row stride ldx) into q as Rp x Kp int8 rows, Rp = roundup(R, 256),
+ * Kp = roundup(K, 128), zero-padded; q (16-byte aligned) holds
+ * mg_i8_packed_size() bytes.  mg_gemm_i8_packed multiplies packed op(A)
+ * (R = M) and packed op(B)^T (R = N) with the semantics of mg_gemm_i8
+ * (argument codes: M -1, N -2, K -3, qA -5, qB -6, C -8, ldc -9).
+ */
+int mg_i8_packed_size(int64_t R, int64_t K, size_t *bytes);
+int mg_i8_pack(char trans, int64_t R, int64_t K, const int8_t *X, int64_t ldx, int8_t *q, void *stream);
+int mg_gemm_i8_packed(int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t *qA,
+                      const int8_t *qB, int32_t beta, int32_t *C, int64_t ldc, void *stream);
 
 /*
  * Tile configurations (the blocking parameters of Section 3.1, Eq. 1-7, as

@@ -90,6 +90,41 @@ def gemm(A, B, C=None, *, alpha: float = 1.0, beta: float = 0.0, path="fp32", wo
     return C
 
 
+def gemm_i8(A, B, C=None, *, alpha: int = 1, beta: int = 0, workspace=None):
+    """C <- alpha * A @ B + beta * C with int8 A (M x K) and B (K x N) and
+    int32 C, alpha, beta (sums exact, result modulo 2^32).  A and B may be
+    row-major or transposed views; C must have unit column stride."""
+    import torch
+    if A.dtype != torch.int8 or B.dtype != torch.int8:
+        raise TypeError("A and B must be int8")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("A and B must be on the GPU")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError(f"inner dimensions differ: {tuple(A.shape)} x {tuple(B.shape)}")
+    if C is None:
+        if beta != 0:
+            raise ValueError("beta != 0 needs an input C")
+        C = torch.empty((M, N), dtype=torch.int32, device=A.device)
+    if C.dtype != torch.int32 or tuple(C.shape) != (M, N) or not C.is_cuda:
+        raise ValueError("C must be an int32 M x N GPU tensor")
+    if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
+        raise ValueError("C must have unit column stride")
+    tA, lda = operand_layout(A)
+    tB, ldb = operand_layout(B)
+    need = _native.mg_gemm_i8_workspace_size(M, N, K)
+    ws_ptr, ws_bytes = None, 0
+    if need:
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = _native.mg_gemm_i8(tA, tB, M, N, K, int(alpha), A.data_ptr(), lda, B.data_ptr(), ldb, int(beta),
+                            C.data_ptr(), max(C.stride(0), N, 1), ws_ptr, ws_bytes, _stream_ptr(A.device))
+    check(st, "mg_gemm_i8")
+    return C
+
+
 def gemm_batched(problems, *, path="fp32", workspace=None):
     """Run a list of GEMMs in ONE persistent kernel launch.
 

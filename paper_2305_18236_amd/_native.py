@@ -71,6 +71,17 @@ def lib():
     L.mg_fp8_pack.restype = ci
     L.mg_gemm_fp8_packed.argtypes = [i64, i64, i64, f32, vp, vp, vp, vp, f32, vp, i64, vp]
     L.mg_gemm_fp8_packed.restype = ci
+    i32 = ctypes.c_int32
+    L.mg_gemm_i8.argtypes = [ch, ch, i64, i64, i64, i32, vp, i64, vp, i64, i32, vp, i64, vp, sz, vp]
+    L.mg_gemm_i8.restype = ci
+    L.mg_gemm_i8_workspace_size.argtypes = [i64, i64, i64]
+    L.mg_gemm_i8_workspace_size.restype = sz
+    L.mg_i8_packed_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    L.mg_i8_packed_size.restype = ci
+    L.mg_i8_pack.argtypes = [ch, i64, i64, vp, i64, vp, vp]
+    L.mg_i8_pack.restype = ci
+    L.mg_gemm_i8_packed.argtypes = [i64, i64, i64, i32, vp, vp, i32, vp, i64, vp]
+    L.mg_gemm_i8_packed.restype = ci
     L.mg_load_tuning.argtypes = [ctypes.c_char_p]
     L.mg_load_tuning.restype = ci
     L.mg_tuned_config.argtypes = [ci, i64, i64, i64]
@@ -146,6 +157,30 @@ def mg_fp8_pack(trans, R, K, X, ldx, q, scales, stream) -> int:
 
 def mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream) -> int:
     return lib().mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream)
+
+
+def mg_gemm_i8(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace, workspace_bytes,
+               stream) -> int:
+    return lib().mg_gemm_i8(_c(transA), _c(transB), M, N, K, int(alpha), A, lda, B, ldb, int(beta), C, ldc,
+                            workspace, workspace_bytes, stream)
+
+
+def mg_gemm_i8_workspace_size(M, N, K) -> int:
+    return int(lib().mg_gemm_i8_workspace_size(M, N, K))
+
+
+def mg_i8_packed_size(R, K) -> int:
+    b = ctypes.c_size_t()
+    check(lib().mg_i8_packed_size(R, K, ctypes.byref(b)), "mg_i8_packed_size")
+    return int(b.value)
+
+
+def mg_i8_pack(trans, R, K, X, ldx, q, stream) -> int:
+    return lib().mg_i8_pack(_c(trans), R, K, X, ldx, q, stream)
+
+
+def mg_gemm_i8_packed(M, N, K, alpha, qA, qB, beta, C, ldc, stream) -> int:
+    return lib().mg_gemm_i8_packed(M, N, K, int(alpha), qA, qB, int(beta), C, ldc, stream)
 
 
 def mg_load_tuning(path) -> int:

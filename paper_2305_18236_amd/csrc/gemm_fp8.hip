@@ -31,6 +31,7 @@
 //   Rp = roundup(R, 256), Kp = roundup(K, 128).
 #include "common.h"
 #include "kernels.h"
+#include "tile_bytes.h"
 
 namespace mg {
 
@@ -140,37 +141,6 @@ hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, i
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// One packed FP8 operand panel (ROWS rows of BK = 128 codes), staged through
-// registers into LDS rows of LDR bytes.  Eight lanes copy one 128-byte row.
-template <int ROWS, int NT, int LDR>
-struct Fp8Panel {
-    static constexpr int CHUNKS = ROWS * 128 / 16;
-    static constexpr int PER = CHUNKS / NT;
-    static_assert(CHUNKS % NT == 0, "panels must split evenly");
-    uint4 v[PER];
-
-    MG_DEVICE void load(const uint8_t* __restrict__ q, int64_t ldq, int64_t row0, int64_t k0, int tid)
-    {
-        const uint8_t* __restrict__ base = q + row0 * ldq + k0;
-        const uint32_t ld32 = uint32_t(ldq);
-#pragma unroll
-        for (int s = 0; s < PER; ++s) {
-            const uint32_t id = tid + s * NT;
-            v[s] = load16u(base, (id / 8) * ld32 + 16 * (id % 8));
-        }
-    }
-
-    MG_DEVICE void store(uint8_t* lds, int tid) const
-    {
-#pragma unroll
-        for (int s = 0; s < PER; ++s) {
-            const int id = tid + s * NT;
-            *reinterpret_cast<uint4*>(&lds[(id / 8) * LDR + 16 * (id % 8)]) = v[s];
-        }
-    }
-};
-
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void gemm_fp8_kernel(Fp8Args g)
@@ -193,8 +163,8 @@ void gemm_fp8_kernel(Fp8Args g)
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
-    Fp8Panel<BM, NT, LDR> pa;
-    Fp8Panel<BN, NT, LDR> pb;
+    BytePanel<BM, NT, LDR> pa;
+    BytePanel<BN, NT, LDR> pb;
 
     floatx16 acc[V][H];
 #pragma unroll

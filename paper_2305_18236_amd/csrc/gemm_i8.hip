@@ -1,0 +1,258 @@
+// INT8 path: 8-bit integer operands with exact 32-bit integer accumulation on
+// the integer matrix cores of gfx950 (v_mfma_i32_32x32x32_i8), the 8-bit
+// integer row of the paper's Table 1 (there a rank-4 update per instruction;
+// here rank 32).
+//
+// Two stages, the same layering as the FP8 path (gemm_fp8.hip):
+//
+// 1. Pack (i8_pack_kernel): op(A) (M x K) and op(B)^T (N x K) are copied once
+//    into a workspace as k-contiguous rows, rows padded to a multiple of 256
+//    and K to a multiple of 128 with zeros (zeros add nothing to the sums), so
+//    the GEMM needs no bounds checks on its loads.  A source that is already
+//    k-contiguous (A stored M x K, B stored N x K) is copied; the other
+//    layouts are transposed through LDS.
+// 2. GEMM (gemm_i8_kernel): workgroup tiles, an in-kernel loop over 128-deep
+//    K panels copied into LDS, and a wave micro-kernel whose int32
+//    accumulators live for the whole K loop.  The epilogue computes
+//    alpha*acc + beta*C0 modulo 2^32 (two's complement); C0 is not read when
+//    beta == 0.  With K <= 131071 no partial sum leaves the int32 range
+//    (|a*b| <= 2^14), so the accumulation itself is exact.
+//
+// MFMA 32x32x32 i8 operand layout: lane l supplies 16 consecutive k of op(A)
+// row l%32 and the same 16 k of op(B) column l%32 (k block l/32); result
+// register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32].
+#include "common.h"
+#include "kernels.h"
+#include "tile_bytes.h"
+
+namespace mg {
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
+
+constexpr int IT = 128;          // pack tile (rows x bytes)
+constexpr int IROW = IT + 16;    // LDS row of the pack tile (bytes)
+
+// One workgroup of 256 threads per 128 x 128 tile of the logical R x Kd
+// matrix op(X).  T == false: X stored R x Kd (k contiguous); T == true:
+// stored Kd x R.  vec: 16-byte aligned X with ldx % 16 == 0.
+template <bool T>
+__global__ __launch_bounds__(256) void i8_pack_kernel(const int8_t* __restrict__ X, int64_t ldx, int64_t R,
+                                                      int64_t Kd, int vec, int8_t* __restrict__ q, int64_t ldq)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[IT * IROW];
+    const int tid = threadIdx.x;
+    const int64_t k0 = int64_t(blockIdx.x) * IT, r0 = int64_t(blockIdx.y) * IT;
+    const int64_t sr0 = T ? k0 : r0, sc0 = T ? r0 : k0;      // stored tile origin
+    const int64_t SRn = T ? Kd : R, SCn = T ? R : Kd;         // stored valid extent
+
+    // 4 chunks of 16 stored bytes per thread: chunk id covers stored row
+    // id / 8 and stored columns 16*(id % 8) .. +15.
+    uint4 v[4];
+    if (vec && sr0 + IT <= SRn && sc0 + IT <= SCn) {          // wave-uniform: interior tile
+        const int8_t* __restrict__ base = X + sr0 * ldx + sc0;
+        const uint32_t ld32 = uint32_t(ldx);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint32_t id = tid + 256 * s;
+            v[s] = load16u(base, (id / 8) * ld32 + 16 * (id % 8));
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int id = tid + 256 * s;
+            const int64_t gr = sr0 + id / 8, gc = sc0 + 16 * (id % 8);
+            uint8_t b[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                b[e] = (gr < SRn && gc + e < SCn) ? uint8_t(X[gr * ldx + gc + e]) : uint8_t(0);
+            uint32_t w[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                w[d] = uint32_t(b[4 * d]) | (uint32_t(b[4 * d + 1]) << 8) | (uint32_t(b[4 * d + 2]) << 16) |
+                       (uint32_t(b[4 * d + 3]) << 24);
+            v[s] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int id = tid + 256 * s;
+        const int sr = id / 8, scol = 16 * (id % 8);
+        if (!T) {
+            // stored row = logical row, columns = k .. k+15
+            *reinterpret_cast<uint4*>(&tile[sr * IROW + scol]) = v[s];
+        } else {
+            // stored row = k, columns = 16 consecutive logical rows
+            const uint32_t w[4] = {v[s].x, v[s].y, v[s].z, v[s].w};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) tile[(scol + e) * IROW + sr] = uint8_t(w[e >> 2] >> (8 * (e & 3)));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int id = tid + 256 * s;
+        const int r = id / 8, c = 16 * (id % 8);
+        *reinterpret_cast<uint4*>(q + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tile[r * IROW + c]);
+    }
+}
+
+hipError_t launch_i8_pack(bool trans, const int8_t* X, int64_t ldx, int64_t R, int64_t Kd, bool vec, int8_t* q,
+                          int64_t ldq, int64_t Rp, int64_t Kp, hipStream_t stream)
+{
+    const dim3 grid(unsigned(Kp / IT), unsigned(Rp / IT)), block(256);
+    if (trans) hipLaunchKernelGGL(i8_pack_kernel<true>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq);
+    else hipLaunchKernelGGL(i8_pack_kernel<false>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq);
+    return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_i8_kernel(I8Args g)
+{
+    constexpr int BK = 128;
+    constexpr int LDR = BK + 16;            // bytes per packed LDS row (padded)
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NT = (BM / WM) * WAVES_N * 64;
+    constexpr int V = WM / 32, H = WN / 32;
+
+    __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * LDR];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LDR];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+    const uint8_t* qA = reinterpret_cast<const uint8_t*>(g.qA);
+    const uint8_t* qB = reinterpret_cast<const uint8_t*>(g.qB);
+
+    BytePanel<BM, NT, LDR> pa;
+    BytePanel<BN, NT, LDR> pb;
+
+    intx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+    const int nk = int(g.Kp / BK);
+    pa.load(qA, g.ldq, m0, 0, tid);
+    pb.load(qB, g.ldq, n0, 0, tid);
+    pa.store(As[0], tid);
+    pb.store(Bs[0], tid);
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        // One basic block per panel with the next panel's fetch issued before
+        // the MFMAs (the last panel re-fetches itself and packs into the
+        // buffer nobody reads any more).
+        const int kn = kt + 1 < nk ? kt + 1 : kt;
+        pa.load(qA, g.ldq, m0, int64_t(kn) * BK, tid);
+        pb.load(qB, g.ldq, n0, int64_t(kn) * BK, tid);
+        __builtin_amdgcn_sched_barrier(0);
+
+#pragma unroll
+        for (int s = 0; s < BK / 32; ++s) {
+            const int koff = 32 * s + 16 * h;
+            intx4 a[V], b[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                a[i] = *reinterpret_cast<const intx4*>(&As[cur][(wm0 + 32 * i + c) * LDR + koff]);
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+                b[j] = *reinterpret_cast<const intx4*>(&Bs[cur][(wn0 + 32 * j + c) * LDR + koff]);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+
+        // keep the pack, which waits for the loads above, after the MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        pa.store(As[cur ^ 1], tid);
+        pb.store(Bs[cur ^ 1], tid);
+        __syncthreads();
+    }
+
+    // C = alpha*acc + beta*C0 modulo 2^32 (unsigned arithmetic wraps).
+    const uint32_t alpha = uint32_t(g.alpha), beta = uint32_t(g.beta);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (m >= g.M) continue;
+            int32_t* crow = g.C + m * g.ldc;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int64_t n = n0 + wn0 + 32 * j + c;
+                if (n < g.N) {
+                    uint32_t o = alpha * uint32_t(acc[i][j][r]);
+                    if (beta != 0u) o += beta * uint32_t(crow[n]);
+                    crow[n] = int32_t(o);
+                }
+            }
+        }
+    }
+}
+
+// C = beta * C modulo 2^32 (beta == 0 writes zeros without reading C): the
+// quick return for alpha == 0 or K == 0.
+__global__ __launch_bounds__(256) void scale_c_i32_kernel(int32_t* C, int64_t M, int64_t N, int64_t ldc,
+                                                          int32_t beta)
+{
+    const int64_t total = M * N;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = t / N, j = t % N;
+        int32_t* p = C + i * ldc + j;
+        *p = (beta == 0) ? 0 : int32_t(uint32_t(beta) * uint32_t(*p));
+    }
+}
+
+hipError_t launch_scale_c_i32(int32_t* C, int64_t M, int64_t N, int64_t ldc, int32_t beta, hipStream_t stream)
+{
+    int64_t blocks = (M * N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(scale_c_i32_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, C, M, N, ldc, beta);
+    return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_i8_cfg(I8Args g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_i8_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    return hipGetLastError();
+}
+
+const SgemmConfig kI8Configs[] = {
+    // id, BM, BN, BK, WM, WN
+    {0, 256, 256, 128, 128, 64},
+    {1, 128, 128, 128, 64, 64},
+    {2, 64, 64, 128, 32, 32},
+};
+const int kNumI8Configs = sizeof(kI8Configs) / sizeof(kI8Configs[0]);
+
+hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream)
+{
+    switch (cfg) {
+    case 0: return launch_i8_cfg<256, 256, 128, 64>(g, stream);
+    case 1: return launch_i8_cfg<128, 128, 64, 64>(g, stream);
+    case 2: return launch_i8_cfg<64, 64, 32, 32>(g, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mg

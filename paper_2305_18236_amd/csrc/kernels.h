@@ -65,6 +65,23 @@ int batched_blocks_per_cu(int path);
 
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
+// INT8 GEMM on packed operands (see gemm_i8.hip).
+struct I8Args {
+    const int8_t* qA;    // Mp x Kp int8 rows of op(A), row stride ldq
+    const int8_t* qB;    // Np x Kp int8 rows of op(B)^T, row stride ldq
+    int32_t* C;
+    int64_t M, N, Kp;
+    int64_t ldq, ldc;
+    int32_t alpha, beta;
+    int tiles_m, tiles_n, group_m;
+};
+extern const SgemmConfig kI8Configs[];
+extern const int kNumI8Configs;
+hipError_t launch_i8_pack(bool trans, const int8_t* X, int64_t ldx, int64_t R, int64_t Kd, bool vec, int8_t* q,
+                          int64_t ldq, int64_t Rp, int64_t Kp, hipStream_t stream);
+hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream);
+hipError_t launch_scale_c_i32(int32_t* C, int64_t M, int64_t N, int64_t ldc, int32_t beta, hipStream_t stream);
+
 // Number of K ranges of a split-K launch described by g (1: no split).
 inline unsigned split_count(const GemmArgs& g)
 {

@@ -18,27 +18,31 @@ namespace {
 bool is_n(char t) { return t == 'N' || t == 'n'; }
 bool is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 
-constexpr int kPaths = 5;
-std::atomic<int> g_forced[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}};
-std::atomic<int> g_forced_splits[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}};
+// Configuration tables: the five mg_path values and MG_CONFIGS_I8.
+constexpr int kPaths = 6;
+std::atomic<int> g_forced[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_forced_splits[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 
 bool valid_path(int path) { return path >= 0 && path < kPaths; }
+
+// Paths of mg_gemm (FP32 operands).
+bool float_path(int path) { return path >= 0 && path <= MG_PATH_FP16; }
 
 // Paths the 16-bit matrix-core kernels run, and their TERMS kind.
 bool is_16bit(int path) { return path == MG_PATH_BF16X3 || path == MG_PATH_BF16 || path == MG_PATH_FP16; }
 int kind_of(int path) { return path == MG_PATH_BF16X3 ? 3 : path == MG_PATH_FP16 ? 16 : 1; }
 
 // Paths the persistent batched kernel runs.
-bool batched_path(int path) { return valid_path(path) && path != MG_PATH_FP8_T128; }
+bool batched_path(int path) { return float_path(path) && path != MG_PATH_FP8_T128; }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP - int(e); }
 
 // rows * ld must stay addressable; both are non-negative here.
 bool fits(int64_t rows, int64_t ld) { return rows == 0 || ld <= INT64_MAX / 4 / rows; }
 
-// BLAS-style validation of the mg_sgemm argument list.
-int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, const float* A,
-             int64_t lda, const float* B, int64_t ldb, const float* C, int64_t ldc)
+// BLAS-style validation of the mg_sgemm argument list (any element type).
+int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, const void* A,
+             int64_t lda, const void* B, int64_t ldb, const void* C, int64_t ldc)
 {
     if (!is_n(transA) && !is_t(transA)) return -1;
     if (!is_n(transB) && !is_t(transB)) return -2;
@@ -78,6 +82,7 @@ ConfigTable table_of(int path)
     case MG_PATH_BF16:
     case MG_PATH_FP16: return {mg::kBf16Configs, mg::kNumBf16Configs};
     case MG_PATH_FP8_T128: return {mg::kFp8Configs, mg::kNumFp8Configs};
+    case MG_CONFIGS_I8: return {mg::kI8Configs, mg::kNumI8Configs};
     default: return {nullptr, 0};
     }
 }
@@ -143,6 +148,11 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         if (tiles(M, N, 256, 256) >= 256) return 4;
         if (tiles(M, N, 128, 128) >= 128) return 2;
         return 3;
+    }
+    if (path == MG_CONFIGS_I8) {
+        if (tiles(M, N, 256, 256) >= 256) return 0;
+        if (tiles(M, N, 128, 128) >= 128) return 1;
+        return 2;
     }
     if ((path == MG_PATH_BF16 || path == MG_PATH_FP16) && tiles(M, N, 128, 128) >= 1024)
         return 2;   // pre-packed: 128 x 128 best
@@ -232,7 +242,7 @@ struct SplitPlan {
 SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
 {
     SplitPlan p{1, 0, 0, 0, 0};
-    if (path == MG_PATH_FP8_T128 || M <= 0 || N <= 0 || K < 2 * kSplitGrain) return p;
+    if (path == MG_PATH_FP8_T128 || path == MG_CONFIGS_I8 || M <= 0 || N <= 0 || K < 2 * kSplitGrain) return p;
     const mg::SgemmConfig& c = table_of(path).cfgs[cfg];
     int s = g_forced_splits[path].load();
     if (s < 0) s = auto_splits(tiles(M, N, c.bm, c.bn), K);
@@ -244,6 +254,44 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
     p.stride = M * p.ldp;
     p.bytes = align256(size_t(p.splits) * size_t(p.stride) * sizeof(float));
     return p;
+}
+
+// ---- INT8 packed layout: Rp x Kp int8 rows (Rp = roundup(R, 256), Kp =
+// roundup(K, 128)); the longest K whose sums stay inside int32.
+constexpr int64_t kMaxI8K = 131071;
+
+struct I8Workspace {
+    size_t qa, qb, total;
+};
+
+I8Workspace i8_workspace(int64_t M, int64_t N, int64_t K)
+{
+    I8Workspace w{};
+    w.qa = 0;
+    w.qb = align256(fp8_q_bytes(M, K));
+    w.total = w.qb + align256(fp8_q_bytes(N, K));
+    return w;
+}
+
+int run_i8_pack(bool trans, int64_t R, int64_t K, const int8_t* X, int64_t ldx, int8_t* q, hipStream_t stream)
+{
+    const bool vec = aligned16(X) && ldx % 16 == 0;
+    return hip_status(mg::launch_i8_pack(trans, X, ldx, R, K, vec, q, fp8_kp(K), fp8_rows(R), fp8_kp(K), stream));
+}
+
+int pick_config(int path, int64_t M, int64_t N, int64_t K);
+
+int run_i8_packed(int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t* qA, const int8_t* qB, int32_t beta,
+                  int32_t* C, int64_t ldc, hipStream_t stream)
+{
+    const int cfg = pick_config(MG_CONFIGS_I8, M, N, K);
+    mg::I8Args g{};
+    g.qA = qA; g.qB = qB; g.C = C;
+    g.M = M; g.N = N; g.Kp = fp8_kp(K);
+    g.ldq = g.Kp; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.group_m = 4;
+    return hip_status(mg::launch_gemm_i8(cfg, g, stream));
 }
 
 int run_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* qA, const uint8_t* sA,
@@ -394,7 +442,7 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
 {
     int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
     if (st != MG_OK) return st;
-    if (table_of(path).n == 0) return MG_ERR_UNSUPPORTED;
+    if (!float_path(path)) return MG_ERR_UNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (path == MG_PATH_FP8_T128) {
         const size_t need = fp8_workspace(M, N, K).total;
@@ -450,7 +498,7 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
 {
     (void)transA; (void)transB;
-    if (M <= 0 || N <= 0 || K <= 0 || table_of(path).n == 0) return 0;
+    if (M <= 0 || N <= 0 || K <= 0 || !float_path(path)) return 0;
     if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
     size_t total = 0;
     if (is_16bit(path) && bf16_prepack_pays(path, M, N, K))
@@ -503,6 +551,80 @@ int mg_gemm_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8
         return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
     }
     return run_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, s);
+}
+
+size_t mg_gemm_i8_workspace_size(int64_t M, int64_t N, int64_t K)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    return i8_workspace(M, N, K).total;
+}
+
+int mg_gemm_i8(char transA, char transB, int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t* A,
+               int64_t lda, const int8_t* B, int64_t ldb, int32_t beta, int32_t* C, int64_t ldc,
+               void* workspace, size_t workspace_bytes, void* stream)
+{
+    int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
+    if (st != MG_OK) return st;
+    if (K > kMaxI8K) return MG_ERR_TOO_LARGE;
+    const bool product = M > 0 && N > 0 && K > 0 && alpha != 0;
+    if (product && (workspace == nullptr || workspace_bytes < i8_workspace(M, N, K).total ||
+                    (reinterpret_cast<uintptr_t>(workspace) & 255) != 0))
+        return MG_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (M == 0 || N == 0) return MG_OK;
+    if (!product) {
+        if (beta == 1) return MG_OK;
+        return hip_status(mg::launch_scale_c_i32(C, M, N, ldc, beta, s));
+    }
+    const I8Workspace w = i8_workspace(M, N, K);
+    int8_t* base = static_cast<int8_t*>(workspace);
+    st = run_i8_pack(is_t(transA), M, K, A, lda, base + w.qa, s);
+    if (st != MG_OK) return st;
+    // op(B)^T is N x K: stored as is when transB is 'T', transposed when 'N'.
+    st = run_i8_pack(!is_t(transB), N, K, B, ldb, base + w.qb, s);
+    if (st != MG_OK) return st;
+    return run_i8_packed(M, N, K, alpha, base + w.qa, base + w.qb, beta, C, ldc, s);
+}
+
+int mg_i8_packed_size(int64_t R, int64_t K, size_t* bytes)
+{
+    if (R < 0) return -1;
+    if (K < 0) return -2;
+    if (bytes) *bytes = fp8_q_bytes(R, K);
+    return MG_OK;
+}
+
+int mg_i8_pack(char trans, int64_t R, int64_t K, const int8_t* X, int64_t ldx, int8_t* q, void* stream)
+{
+    if (!is_n(trans) && !is_t(trans)) return -1;
+    if (R < 0) return -2;
+    if (K < 0) return -3;
+    if (X == nullptr && R > 0 && K > 0) return -4;
+    const int64_t cols = is_t(trans) ? R : K, rows = is_t(trans) ? K : R;
+    if (ldx < (cols > 1 ? cols : 1) || !fits(rows, ldx)) return -5;
+    if (q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) != 0) return -6;
+    if (R > INT_MAX || K > kMaxI8K) return MG_ERR_TOO_LARGE;
+    return run_i8_pack(is_t(trans), R, K, X, ldx, q, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mg_gemm_i8_packed(int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t* qA, const int8_t* qB,
+                      int32_t beta, int32_t* C, int64_t ldc, void* stream)
+{
+    if (M < 0) return -1;
+    if (N < 0) return -2;
+    if (K < 0) return -3;
+    if (qA == nullptr || (reinterpret_cast<uintptr_t>(qA) & 15) != 0) return -5;
+    if (qB == nullptr || (reinterpret_cast<uintptr_t>(qB) & 15) != 0) return -6;
+    if (C == nullptr && M > 0 && N > 0) return -8;
+    if (ldc < (N > 1 ? N : 1) || !fits(M, ldc)) return -9;
+    if (M > INT_MAX || N > INT_MAX || K > kMaxI8K) return MG_ERR_TOO_LARGE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (M == 0 || N == 0) return MG_OK;
+    if (K == 0 || alpha == 0) {
+        if (beta == 1) return MG_OK;
+        return hip_status(mg::launch_scale_c_i32(C, M, N, ldc, beta, s));
+    }
+    return run_i8_packed(M, N, K, alpha, qA, qB, beta, C, ldc, s);
 }
 
 int mg_num_configs(int path)
