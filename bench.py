@@ -135,12 +135,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling", "engine"],
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling", "engine", "types", "syr2k"],
                     default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
                          "chain: forward + backward of Y = (X W1) W2; fp8: FP8 path at 8192^3; "
                          "sweep: FP32 shapes x layouts; tiling: Tiling vs Tiling+Packing over sizes; "
-                         "engine: vector-ALU vs matrix-core micro-kernel")
+                         "engine: vector-ALU vs matrix-core micro-kernel; types: FP16 and INT8 at 8192^3; "
+                         "syr2k: SYR2K at N = K = 8192")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -176,6 +177,10 @@ def main():
         return bench_tiling(args, torch, si, native, dev)
     if args.workload == "engine":
         return bench_engine(args, torch, si, native, dev)
+    if args.workload == "types":
+        return bench_types(args, torch, si, native, dev)
+    if args.workload == "syr2k":
+        return bench_syr2k(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -586,6 +591,131 @@ def bench_engine(args, torch, si, native, dev):
                         "unit": "TFLOP/s", "frac": big["valu"]["frac_of_valu_peak"], "traffic": None,
                         "kernel": f"sgemm_valu_kernel (config {big['valu']['config']}) at 8192^3"},
            "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+INT8_PEAK_TOPS = 5033.2
+
+
+def bench_types(args, torch, si, native, dev):
+    """Table 1's other operand types at 8192^3 NN: the FP16 path (FP32
+    operands rounded to binary16, end to end) and the INT8 entry points (int8
+    operands, int32 C; end to end including the pack, and the GEMM alone on
+    packed operands).  alpha 1, beta 0 (INT8: alpha 1, beta 0)."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    n = M
+    flops = 2.0 * n ** 3
+    A = torch.from_numpy(si.uniform((n * n,), si.seed_for(3, "A"))).to(dev)
+    B = torch.from_numpy(si.uniform((n * n,), si.seed_for(3, "B"))).to(dev)
+    C = torch.zeros(n * n, device=dev)
+    need = native.mg_gemm_workspace_size(4, "N", "N", n, n, n)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+    def fp16():
+        native.check(native.mg_gemm(4, "N", "N", n, n, n, 1.0, A.data_ptr(), n, B.data_ptr(), n, 0.0,
+                                    C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+
+    fp16_ms = _time_ms(fp16, args.steps, args.warmup, torch, stream)
+    del A, B, C, ws
+    g = torch.Generator(device=dev)
+    g.manual_seed(si.seed_for(3, "A"))
+    Ai = torch.randint(-128, 128, (n * n,), dtype=torch.int8, device=dev, generator=g)
+    Bi = torch.randint(-128, 128, (n * n,), dtype=torch.int8, device=dev, generator=g)
+    Ci = torch.zeros(n * n, dtype=torch.int32, device=dev)
+    need = native.mg_gemm_i8_workspace_size(n, n, n)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def i8_full():
+        native.check(native.mg_gemm_i8("N", "N", n, n, n, 1, Ai.data_ptr(), n, Bi.data_ptr(), n, 0, Ci.data_ptr(),
+                                       n, ws.data_ptr(), need, sp), "mg_gemm_i8")
+
+    i8_ms = _time_ms(i8_full, args.steps, args.warmup, torch, stream)
+    q = native.mg_i8_packed_size(n, n)
+    qA, qB = ws[:q], ws[need - q:]
+
+    def i8_gemm():
+        native.check(native.mg_gemm_i8_packed(n, n, n, 1, qA.data_ptr(), qB.data_ptr(), 0, Ci.data_ptr(), n, sp),
+                     "mg_gemm_i8_packed")
+
+    i8g_ms = _time_ms(i8_gemm, args.steps, args.warmup, torch, stream)
+    rows = {
+        "fp16": {"ms": round(fp16_ms, 4), "tflops": round(flops / fp16_ms / 1e9, 1),
+                 "frac_of_fp16_peak": round(flops / fp16_ms / 1e9 / PEAK_TFLOPS["bf16"], 3),
+                 "config": native.mg_tuned_config(4, n, n, n)},
+        "int8_end_to_end": {"ms": round(i8_ms, 4), "tops": round(flops / i8_ms / 1e9, 1),
+                            "frac_of_int8_peak": round(flops / i8_ms / 1e9 / INT8_PEAK_TOPS, 3)},
+        "int8_gemm_only": {"ms": round(i8g_ms, 4), "tops": round(flops / i8g_ms / 1e9, 1),
+                           "frac_of_int8_peak": round(flops / i8g_ms / 1e9 / INT8_PEAK_TOPS, 3),
+                           "config": native.mg_tuned_config(5, n, n, n)},
+    }
+    out = {"metric": "FP16 TFLOP/s and INT8 TOP/s at 8192^3", "unit": "TOP/s",
+           "value": rows["int8_gemm_only"]["tops"], "ms_per_step": rows["int8_gemm_only"]["ms"], "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "config": {"workload": "fp16_int8_8192x8192x8192_nn", "fp16_inputs": "uniform[-1,1] float32",
+                      "int8_inputs": "uniform integers in [-128, 127]"},
+           "roofline": {"bound": "mfma", "achieved": rows["int8_gemm_only"]["tops"], "peak": INT8_PEAK_TOPS,
+                        "unit": "TOP/s", "frac": rows["int8_gemm_only"]["frac_of_int8_peak"], "traffic": None,
+                        "kernel": "gemm_i8_kernel<256,256,128,64>"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_syr2k(args, torch, si, native, dev):
+    """SYR2K (Section 5.1) on the lower triangle, N = K = 8192, trans 'N',
+    alpha 1.5, beta 0.5: one launch over the triangle's tiles, both products
+    in one accumulator.  Work counted as 2*N^2*K (the triangle's N(N+1)/2
+    entries, two K-long dot products each).  Beside it, the same update done
+    with two full FP32 GEMMs (C += alpha*A*B^T, then C += alpha*B*A^T over the
+    whole square), the way it would be written without SYR2K."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    n = k = M
+    X = torch.from_numpy(si.uniform((n * k,), si.seed_for(5, "X"))).to(dev)
+    Y = torch.from_numpy(si.uniform((n * k,), si.seed_for(5, "W1"))).to(dev)
+    C = torch.from_numpy(si.uniform((n * n,), si.seed_for(5, "C"))).to(dev)
+
+    need = native.mg_syr2k_workspace_size(0, n, k)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+    def run(splits):
+        native.check(native.mg_force_splits(0, splits), "mg_force_splits")
+        try:
+            w = native.mg_syr2k_workspace_size(0, n, k)
+
+            def syr2k():
+                native.check(native.mg_syr2k(0, "L", "N", n, k, ALPHA, X.data_ptr(), k, Y.data_ptr(), k, BETA,
+                                             C.data_ptr(), n, ws.data_ptr(), w, sp), "mg_syr2k")
+
+            return _time_ms(syr2k, args.steps, args.warmup, torch, stream)
+        finally:
+            native.mg_force_splits(0, -1)
+
+    ms = run(-1)                       # the automatic plan
+    auto_splits = need // (4 * n * n) if need else 1
+    ms_unsplit = run(1)
+
+    def two_gemms():
+        native.check(native.mg_gemm(0, "N", "T", n, n, k, ALPHA, X.data_ptr(), k, Y.data_ptr(), k, BETA,
+                                    C.data_ptr(), n, None, 0, sp), "mg_gemm")
+        native.check(native.mg_gemm(0, "N", "T", n, n, k, ALPHA, Y.data_ptr(), k, X.data_ptr(), k, 1.0,
+                                    C.data_ptr(), n, None, 0, sp), "mg_gemm")
+
+    ms2 = _time_ms(two_gemms, max(2, args.steps // 2), 1, torch, stream)
+    flops = 2.0 * n * n * k
+    tf = flops / (ms * 1e-3) / 1e12
+    out = {"metric": "SYR2K TFLOP/s (2*N^2*K useful flops) at N = K = 8192", "unit": "TFLOP/s",
+           "value": round(tf, 2), "ms_per_step": round(ms, 4), "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "ssyr2k_lower_n_8192x8192", "N": n, "K": k, "uplo": "L", "trans": "N",
+                      "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]"},
+           "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                        "frac": round(tf / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+                        "kernel": f"syr2k_kernel (config {native.mg_tuned_config(0, n, n, k)} tiles)"},
+           "splits": int(auto_splits), "unsplit_ms": round(ms_unsplit, 4),
+           "two_full_gemms": {"ms": round(ms2, 4), "speedup_of_syr2k": round(ms2 / ms, 3)}}
     print(json.dumps(out), flush=True)
 
 

@@ -124,6 +124,29 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB,
                               int64_t M, int64_t N, int64_t K);
 
 /*
+ * SYR2K, the paper's extension of the macro level to another BLAS kernel
+ * (Section 5.1), on one triangle of the symmetric N x N matrix C:
+ *   trans 'N':  C <- alpha*A*B^T + alpha*B*A^T + beta*C   (A, B stored N x K)
+ *   trans 'T':  C <- alpha*A^T*B + alpha*B^T*A + beta*C   (A, B stored K x N)
+ * Row-major like mg_sgemm (lda, ldb >= K for 'N', >= N for 'T'; ldc >= N).
+ * uplo 'L' reads and writes only C[i][j] with i >= j, 'U' only i <= j; the
+ * other strict triangle is never touched.  beta == 0: C is not read;
+ * alpha == 0 or K == 0: the triangle becomes beta*C.  path: MG_PATH_FP32 (the
+ * only one; others return MG_ERR_UNSUPPORTED).  A forced FP32 configuration
+ * must be square (ids 0, 3, 5).  `workspace` (optional, device, 256-byte
+ * aligned, mg_syr2k_workspace_size() bytes) holds partial tiles when each
+ * tile's K loop is split over several workgroups (so that the triangle's
+ * tiles fill the GPU's last round); with NULL or too few bytes the update
+ * runs unsplit.  Partials are summed in a fixed order: results are
+ * deterministic.  Argument codes follow BLAS xSYR2K: uplo -1, trans -2, N -3,
+ * K -4, A -6, lda -7, B -8, ldb -9, C -11, ldc -12.
+ */
+int mg_syr2k(int path, char uplo, char trans, int64_t N, int64_t K, float alpha,
+             const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+             float *C, int64_t ldc, void *workspace, size_t workspace_bytes, void *stream);
+size_t mg_syr2k_workspace_size(int path, int64_t N, int64_t K);
+
+/*
  * INT8 GEMM, the 8-bit integer operand type of the paper's Table 1:
  *   C <- alpha * op(A) * op(B) + beta * C
  * with int8 A and B (device pointers, stored and strided exactly as for

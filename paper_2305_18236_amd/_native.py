@@ -71,6 +71,10 @@ def lib():
     L.mg_fp8_pack.restype = ci
     L.mg_gemm_fp8_packed.argtypes = [i64, i64, i64, f32, vp, vp, vp, vp, f32, vp, i64, vp]
     L.mg_gemm_fp8_packed.restype = ci
+    L.mg_syr2k.argtypes = [ci, ch, ch, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp, sz, vp]
+    L.mg_syr2k.restype = ci
+    L.mg_syr2k_workspace_size.argtypes = [ci, i64, i64]
+    L.mg_syr2k_workspace_size.restype = sz
     i32 = ctypes.c_int32
     L.mg_gemm_i8.argtypes = [ch, ch, i64, i64, i64, i32, vp, i64, vp, i64, i32, vp, i64, vp, sz, vp]
     L.mg_gemm_i8.restype = ci
@@ -157,6 +161,16 @@ def mg_fp8_pack(trans, R, K, X, ldx, q, scales, stream) -> int:
 
 def mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream) -> int:
     return lib().mg_gemm_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, stream)
+
+
+def mg_syr2k(path, uplo, trans, N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace, workspace_bytes,
+             stream) -> int:
+    return lib().mg_syr2k(int(path), _c(uplo), _c(trans), N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace,
+                          workspace_bytes, stream)
+
+
+def mg_syr2k_workspace_size(path, N, K) -> int:
+    return int(lib().mg_syr2k_workspace_size(int(path), N, K))
 
 
 def mg_gemm_i8(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace, workspace_bytes,

@@ -65,6 +65,18 @@ int batched_blocks_per_cu(int path);
 
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);
 
+// SYR2K on one triangle (see gemm_syr2k.hip); g.M == g.N, cfg a square FP32
+// configuration accepted by syr2k_config_supported().
+// splits > 1: the 2 * ceil(K / BK) panels of every tile's K loop are cut into
+// `splits` ranges of g.k_chunk panels (splits == ceil(panels / k_chunk)),
+// each writing a partial tile to g.part (g.ldp, g.part_stride), summed by
+// launch_syr2k_reduce into g.C with g.alpha / g.beta.
+bool syr2k_config_supported(int cfg);
+int syr2k_panel_depth(int cfg);
+hipError_t launch_syr2k(int cfg, bool lower, bool tr, int splits, GemmArgs g, hipStream_t stream);
+hipError_t launch_syr2k_reduce(const GemmArgs& g, int splits, bool lower, hipStream_t stream);
+hipError_t launch_scale_tri(float* C, int64_t N, int64_t ldc, float beta, bool lower, hipStream_t stream);
+
 // INT8 GEMM on packed operands (see gemm_i8.hip).
 struct I8Args {
     const int8_t* qA;    // Mp x Kp int8 rows of op(A), row stride ldq

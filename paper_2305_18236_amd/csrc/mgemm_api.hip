@@ -432,6 +432,62 @@ size_t batched_workspace(int64_t count)
     return count > 0 ? size_t(count) * sizeof(mg::BatchProblem) : 0;
 }
 
+// ---- SYR2K: square tile configuration and split of each tile's K loop.
+// The triangle of T x T tiles has T(T+1)/2 tiles; when that count is not a
+// whole number of rounds over the compute units, the last round runs mostly
+// idle.  Cutting every tile's K loop (both products, 2*ceil(K/BK) panels)
+// into S ranges turns the tiles into S times as many shorter work items; S is
+// chosen to minimise  rounds(S) / S  +  S * r,  the makespan in whole-tile
+// units plus the reduction, which moves 8 bytes per triangle entry and split
+// (r = that traffic's time over one tile's matrix-core time, taken as
+// 0.18 * tiles / K from the measured FP32 rates: 0.53 TFLOP/s per CU, ~6 TB/s).
+struct Syr2kPlan {
+    int cfg, splits;
+    int64_t chunk, ldp, stride;
+    size_t bytes;
+};
+
+Syr2kPlan syr2k_plan(int64_t N, int64_t K)
+{
+    Syr2kPlan p{-1, 1, 0, 0, 0, 0};
+    const int64_t cus = device_cus();
+    auto tri = [&](int64_t b) { const int64_t t = (N + b - 1) / b; return t * (t + 1) / 2; };
+    int cfg = g_forced[MG_PATH_FP32].load();
+    if (cfg >= 0 && !mg::syr2k_config_supported(cfg)) return p;
+    if (cfg < 0) cfg = tri(256) >= cus ? 5 : tri(128) >= cus ? 0 : 3;
+    p.cfg = cfg;
+    const int bt = table_of(MG_PATH_FP32).cfgs[cfg].bm;
+    const int bk = mg::syr2k_panel_depth(cfg);
+    const int64_t tiles_n = tri(bt);
+    const int64_t panels = 2 * ((K + bk - 1) / bk);
+    int s = g_forced_splits[MG_PATH_FP32].load();
+    if (s < 0) {
+        const double r = 0.18 * double(tiles_n) / double(K);
+        double best = 1e30;
+        s = 1;
+        for (int c = 1; c <= kMaxSplits && 2 * K / c >= kMinRange; ++c) {
+            const double rounds = double((tiles_n * c + cus - 1) / cus);
+            const double cost = rounds / c + c * r;
+            if (cost < best - 1e-9) {
+                best = cost;
+                s = c;
+            }
+        }
+    }
+    if (s > 1) {
+        p.chunk = (panels + s - 1) / s;
+        p.splits = int((panels + p.chunk - 1) / p.chunk);
+    }
+    if (p.splits > 1) {
+        p.ldp = round_up(N, 4);
+        p.stride = N * p.ldp;
+        p.bytes = align256(size_t(p.splits) * size_t(p.stride) * sizeof(float));
+    } else {
+        p.chunk = 0;
+    }
+    return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -551,6 +607,61 @@ int mg_gemm_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8
         return hip_status(mg::launch_scale_c(C, M, N, ldc, beta, s));
     }
     return run_fp8_packed(M, N, K, alpha, qA, sA, qB, sB, beta, C, ldc, s);
+}
+
+int mg_syr2k(int path, char uplo, char trans, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+             const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* workspace,
+             size_t workspace_bytes, void* stream)
+{
+    const bool lower = uplo == 'L' || uplo == 'l';
+    if (!lower && uplo != 'U' && uplo != 'u') return -1;
+    if (!is_n(trans) && !is_t(trans)) return -2;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    const bool tr = is_t(trans);
+    const int64_t rows = tr ? K : N, cols = tr ? N : K;   // stored shape of A and B
+    if (A == nullptr && N > 0 && K > 0) return -6;
+    if (lda < (cols > 1 ? cols : 1) || !fits(rows, lda)) return -7;
+    if (B == nullptr && N > 0 && K > 0) return -8;
+    if (ldb < (cols > 1 ? cols : 1) || !fits(rows, ldb)) return -9;
+    if (C == nullptr && N > 0) return -11;
+    if (ldc < (N > 1 ? N : 1) || !fits(N, ldc)) return -12;
+    if (path != MG_PATH_FP32) return MG_ERR_UNSUPPORTED;
+    if (N > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (N == 0) return MG_OK;
+    if (K == 0 || alpha == 0.f) {
+        if (beta == 1.f) return MG_OK;
+        return hip_status(mg::launch_scale_tri(C, N, ldc, beta, lower, s));
+    }
+    const Syr2kPlan plan = syr2k_plan(N, K);
+    if (plan.cfg < 0) return MG_ERR_UNSUPPORTED;
+    const int64_t t = (N + 63) / 64;
+    if (t * (t + 1) / 2 > INT_MAX) return MG_ERR_TOO_LARGE;
+    mg::GemmArgs g{};
+    g.A = A; g.B = B; g.C = C;
+    g.M = N; g.N = N; g.K = K;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.vec_a = fast_operand(A, lda);
+    g.vec_b = fast_operand(B, ldb);
+    g.vec_c = aligned16(C) && ldc % 4 == 0;
+    const bool split = plan.splits > 1 && workspace != nullptr && workspace_bytes >= plan.bytes &&
+                       (reinterpret_cast<uintptr_t>(workspace) & 255) == 0;
+    if (!split) return hip_status(mg::launch_syr2k(plan.cfg, lower, tr, 1, g, s));
+    g.part = static_cast<float*>(workspace);
+    g.k_chunk = plan.chunk;
+    g.ldp = plan.ldp;
+    g.part_stride = plan.stride;
+    hipError_t e = mg::launch_syr2k(plan.cfg, lower, tr, plan.splits, g, s);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(mg::launch_syr2k_reduce(g, plan.splits, lower, s));
+}
+
+size_t mg_syr2k_workspace_size(int path, int64_t N, int64_t K)
+{
+    if (path != MG_PATH_FP32 || N <= 0 || K <= 0) return 0;
+    return syr2k_plan(N, K).bytes;
 }
 
 size_t mg_gemm_i8_workspace_size(int64_t M, int64_t N, int64_t K)

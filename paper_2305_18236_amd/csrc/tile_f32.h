@@ -147,7 +147,14 @@ constexpr int sgemm_lds_floats() { return 2 * BK * (BM + BN); }
 // workgroup ((BM/WM) * (BN/WN) waves).  smem: sgemm_lds_floats() floats of LDS,
 // 16-byte aligned.  Ends with a workgroup barrier after the last LDS read, so
 // the caller may reuse smem for another tile right away.
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+//
+// SYR2K: the K loop runs twice, first over op(A) x op(B), then over the same
+// panels with the roles of A and B exchanged (A read with B's stride as the
+// left operand, B with A's as the right one), accumulating both products into
+// the same registers: alpha*(X Y^T + Y X^T) for the symmetric rank-2k update
+// of Section 5.1 (M == N, both operands of one shape).  UPLO 1 (2) stores
+// only the entries with m >= n (m <= n) of the tile.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SYR2K = false, int UPLO = 0>
 MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
 {
     constexpr int WAVES_N = BN / WN;
@@ -180,11 +187,20 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
     const int64_t Ra = TA ? g.K : g.M, Ca = TA ? g.M : g.K;
     const int64_t Rb = TB ? g.N : g.K, Cb = TB ? g.K : g.N;
 
-    auto fetch = [&](int64_t k0) {
-        if (TA) la.load(g.A, g.lda, k0, m0, Ra, Ca, g.vec_a, tid);
-        else    la.load(g.A, g.lda, m0, k0, Ra, Ca, g.vec_a, tid);
-        if (TB) lb.load(g.B, g.ldb, n0, k0, Rb, Cb, g.vec_b, tid);
-        else    lb.load(g.B, g.ldb, k0, n0, Rb, Cb, g.vec_b, tid);
+    // Panel p of the K loop: segment p / nk (SYR2K's second product swaps
+    // the operands), k0 = (p % nk) * BK.
+    const int nk = int((g.K + BK - 1) / BK);
+    auto fetch = [&](int p) {
+        const bool swap = SYR2K && p >= nk;
+        const int64_t k0 = int64_t(swap ? p - nk : p) * BK;
+        const float* __restrict__ xa = swap ? g.B : g.A;
+        const float* __restrict__ xb = swap ? g.A : g.B;
+        const int64_t lxa = swap ? g.ldb : g.lda, lxb = swap ? g.lda : g.ldb;
+        const bool va = swap ? g.vec_b : g.vec_a, vb = swap ? g.vec_a : g.vec_b;
+        if (TA) la.load(xa, lxa, k0, m0, Ra, Ca, va, tid);
+        else    la.load(xa, lxa, m0, k0, Ra, Ca, va, tid);
+        if (TB) lb.load(xb, lxb, n0, k0, Rb, Cb, vb, tid);
+        else    lb.load(xb, lxb, k0, n0, Rb, Cb, vb, tid);
     };
     auto pack = [&](int buf) {
         la.template store<TA, BM>(As[buf], tid);
@@ -199,18 +215,25 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const int nk = int((g.K + BK - 1) / BK);
-    if (nk > 0) {
-        fetch(0);
+    // Panels [p0, p1) of the whole K loop.  A split SYR2K (gridDim.y > 1)
+    // gives workgroup row s the range of k_chunk panels starting at s*k_chunk;
+    // GEMM splits offset the operands instead (split_k_view) and run it all.
+    int p0 = 0, p1 = SYR2K ? 2 * nk : nk;
+    if (SYR2K && gridDim.y > 1) {
+        p0 = int(blockIdx.y * g.k_chunk);
+        p1 = min(p1, int(p0 + g.k_chunk));
+    }
+    if (p0 < p1) {
+        fetch(p0);
         pack(0);
     }
     __syncthreads();
 
     constexpr int STEPS = BK / 2;          // MFMA k-steps per panel
     constexpr int PACK_AT = STEPS / 2;     // the next panel is packed half-way
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
+    for (int kt = p0; kt < p1; ++kt) {
+        const int cur = (kt - p0) & 1;
+        if (kt + 1 < p1) fetch(kt + 1);
 
         const float* a_rows = As[cur] + h * BM;
         const float* b_rows = Bs[cur] + h * BN;
@@ -267,7 +290,9 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
             float out[H];
 #pragma unroll
             for (int j = 0; j < H; ++j) out[j] = acc[i][j][r];
-            if (H == 4 && g.vec_c && ncol + 3 < g.N) {
+            // columns ncol .. ncol+H-1 all inside the stored triangle
+            const bool whole = UPLO == 0 || (UPLO == 1 ? ncol + H - 1 <= m : ncol >= m);
+            if (H == 4 && g.vec_c && ncol + 3 < g.N && whole) {
                 floatx4 o = {alpha * out[0], alpha * out[1], alpha * out[2], alpha * out[3]};
                 if (beta != 0.f) {
                     const floatx4 c0 = *reinterpret_cast<const floatx4*>(cp);
@@ -280,7 +305,8 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
             } else {
 #pragma unroll
                 for (int j = 0; j < H; ++j) {
-                    if (ncol + j < g.N) {
+                    const bool tri = UPLO == 0 || (UPLO == 1 ? ncol + j <= m : ncol + j >= m);
+                    if (ncol + j < g.N && tri) {
                         float o = alpha * out[j];
                         if (beta != 0.f) o = __builtin_fmaf(alpha, out[j], beta * cp[j]);
                         cp[j] = o;

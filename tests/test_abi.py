@@ -107,3 +107,40 @@ def test_operand_layout_from_strides():
     assert operand_layout(big[:, :7].t()) == ("T", 12)
     with pytest.raises(ValueError):
         operand_layout(torch.empty(4, 6)[:, ::2])
+
+
+def _syr2k(native, **kw):
+    a = dict(path=0, uplo="L", trans="N", N=4, K=6, alpha=1.0, A=FAKE, lda=6, B=FAKE, ldb=6, beta=0.0,
+             C=FAKE, ldc=4)
+    a.update(kw)
+    return native.mg_syr2k(a["path"], a["uplo"], a["trans"], a["N"], a["K"], a["alpha"], a["A"], a["lda"],
+                           a["B"], a["ldb"], a["beta"], a["C"], a["ldc"], None, 0, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(uplo="X"), -1), (dict(trans="Q"), -2), (dict(N=-1), -3), (dict(K=-2), -4), (dict(A=None), -6),
+    (dict(lda=5), -7), (dict(B=None), -8), (dict(ldb=5), -9), (dict(C=None), -11), (dict(ldc=3), -12),
+    # trans 'T': A and B are K x N, so lda, ldb >= N
+    (dict(trans="T", lda=3), -7), (dict(trans="T", lda=4, ldb=3), -9),
+    (dict(path=1), -101), (dict(path=3), -101),
+])
+def test_syr2k_arguments_rejected_on_host(native, kw, code):
+    assert _syr2k(native, **kw) == code
+
+
+def test_syr2k_empty_is_noop(native):
+    assert _syr2k(native, N=0, A=None, B=None, C=None) == 0
+
+
+def test_syr2k_split_plan(native):
+    """A triangle that does not fill whole rounds of the GPU splits its tiles'
+    K loops (when a workspace is given); forced splits are honoured."""
+    assert native.mg_syr2k_workspace_size(0, 8192, 8192) > 0
+    assert native.mg_syr2k_workspace_size(1, 8192, 8192) == 0
+    try:
+        assert native.mg_force_splits(0, 1) == 0
+        assert native.mg_syr2k_workspace_size(0, 8192, 8192) == 0
+        assert native.mg_force_splits(0, 4) == 0
+        assert native.mg_syr2k_workspace_size(0, 100, 1000) == 4 * 100 * 100 * 4
+    finally:
+        native.mg_force_splits(0, -1)
