@@ -358,9 +358,20 @@ def bench_chain(args, torch, si, native, dev):
     print(json.dumps(out), flush=True)
 
 
-def _time_ms(fn, steps, warmup, torch, stream):
-    for _ in range(warmup):
+def _time_ms(fn, steps, warmup, torch, stream, min_warm_ms=150.0):
+    """Mean time of `steps` back-to-back calls on `stream` (HIP events).
+
+    Warm-up runs `warmup` calls and then keeps going until the warm-up has
+    taken `min_warm_ms` of wall time: after the host has prepared fresh inputs
+    the GPU has idled and its clock ramps back up over tens of milliseconds,
+    which would otherwise be charged to the first timed case."""
+    t0 = time.perf_counter()
+    n = 0
+    while n < warmup or (time.perf_counter() - t0) * 1e3 < min_warm_ms:
         fn()
+        n += 1
+        if n >= warmup:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
