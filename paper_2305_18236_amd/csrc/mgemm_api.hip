@@ -32,6 +32,9 @@ bool float_path(int path) { return path >= 0 && path <= MG_PATH_FP16; }
 bool is_16bit(int path) { return path == MG_PATH_BF16X3 || path == MG_PATH_BF16 || path == MG_PATH_FP16; }
 int kind_of(int path) { return path == MG_PATH_BF16X3 ? 3 : path == MG_PATH_FP16 ? 16 : 1; }
 
+// Whether configuration `cfg` of `path`'s table runs on that path.
+bool config_valid(int path, int cfg);
+
 // Paths the persistent batched kernel runs.
 bool batched_path(int path) { return float_path(path) && path != MG_PATH_FP8_T128; }
 
@@ -101,6 +104,11 @@ void table_clear()
     std::memset(g_table, -1, sizeof(g_table));
 }
 
+bool config_valid(int path, int cfg)
+{
+    return cfg >= 0 && cfg < table_of(path).n;
+}
+
 int bucket(int64_t x)
 {
     if (x <= 1) return 0;
@@ -154,8 +162,6 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         if (tiles(M, N, 128, 128) >= 128) return 1;
         return 2;
     }
-    if ((path == MG_PATH_BF16 || path == MG_PATH_FP16) && tiles(M, N, 128, 128) >= 1024)
-        return 2;   // pre-packed: 128 x 128 best
     // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the
     // paper finds for small matrices (measured: 0.84x the packed time at 16^3,
     // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
@@ -322,7 +328,7 @@ int pick_config(int path, int64_t M, int64_t N, int64_t K)
     int cfg = g_forced[path].load();
     if (cfg >= 0) return cfg;
     cfg = table_lookup(path, M, N, K);
-    if (cfg >= 0 && cfg < table_of(path).n) return cfg;
+    if (config_valid(path, cfg)) return cfg;
     return choose_config(path, M, N, K);
 }
 
@@ -772,7 +778,7 @@ int mg_config_uses_mfma(int path, int index)
 int mg_force_config(int path, int config_id)
 {
     if (!valid_path(path)) return MG_ERR_UNSUPPORTED;
-    if (config_id < -1 || config_id >= mg_num_configs(path)) return MG_ERR_UNSUPPORTED;
+    if (config_id != -1 && !config_valid(path, config_id)) return MG_ERR_UNSUPPORTED;
     g_forced[path].store(config_id);
     return MG_OK;
 }
@@ -822,7 +828,7 @@ int mg_load_tuning(const char* path)
         char mode[8] = "s";
         const int got = std::sscanf(q, "%d %d %d %d %d %7s", &p, &mb, &nb, &kb, &cfg, mode);
         if (got < 5 || !valid_path(p) || mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 ||
-            kb >= kBuckets || cfg < 0 || cfg >= table_of(p).n || !(mode[0] == 's' || mode[0] == 'b') ||
+            kb >= kBuckets || !config_valid(p, cfg) || !(mode[0] == 's' || mode[0] == 'b') ||
             mode[1] != 0) {
             bad = 1;
             break;

@@ -345,22 +345,46 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
         const int cur = kt & 1;
         if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
 
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
+        // Fragment reads of one MFMA k-step.  bf16x3 issues B before A and
+        // the lo halves before the hi ones, in the order its three MFMA groups
+        // consume them (lo(A)*hi(B), hi(A)*lo(B), hi(A)*hi(B)), so the first
+        // group starts while the later fragments are still in flight.  The
+        // single-term kinds, with half the fragment registers, read the next
+        // step's fragments before issuing this step's MFMAs (software
+        // pipelining across the panel's steps).
+        auto read_step = [&](int s, bf16x8 (&xah)[V], bf16x8 (&xal)[V], bf16x8 (&xbh)[H], bf16x8 (&xbl)[H]) {
             const int koff = 16 * s + 8 * h;
-            bf16x8 ah[V], bh[H], al[V], bl[H];
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-                const int off = (wm0 + 32 * i + c) * LDR + koff;
-                ah[i] = *reinterpret_cast<const bf16x8*>(&As[cur][0][off]);
-                if (TERMS == 3) al[i] = *reinterpret_cast<const bf16x8*>(&As[cur][NL - 1][off]);
-            }
 #pragma unroll
             for (int j = 0; j < H; ++j) {
                 const int off = (wn0 + 32 * j + c) * LDR + koff;
-                bh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
-                if (TERMS == 3) bl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
+                xbh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
             }
+            if constexpr (TERMS == 3) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    const int off = (wm0 + 32 * i + c) * LDR + koff;
+                    xal[i] = *reinterpret_cast<const bf16x8*>(&As[cur][NL - 1][off]);
+                }
+#pragma unroll
+                for (int j = 0; j < H; ++j) {
+                    const int off = (wn0 + 32 * j + c) * LDR + koff;
+                    xbl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const int off = (wm0 + 32 * i + c) * LDR + koff;
+                xah[i] = *reinterpret_cast<const bf16x8*>(&As[cur][0][off]);
+            }
+        };
+        constexpr bool PIPE = TERMS != 3;
+        bf16x8 ah[V], bh[H], al[V], bl[H];
+        if (PIPE) read_step(0, ah, al, bh, bl);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            bf16x8 nah[V], nbh[H], nal[V], nbl[H];
+            if (!PIPE) read_step(s, ah, al, bh, bl);
+            else if (s + 1 < STEPS) read_step(s + 1, nah, nal, nbh, nbl);
             if (s == PACK_AT) {
                 // Convert and pack the panel fetched at the top of this
                 // iteration into the other LDS buffer (last read before the
@@ -387,6 +411,12 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
 #pragma unroll
                 for (int j = 0; j < H; ++j)
                     acc[i][j] = mfma16<TERMS>(ah[i], bh[j], acc[i][j]);
+            if (PIPE && s + 1 < STEPS) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) ah[i] = nah[i];
+#pragma unroll
+                for (int j = 0; j < H; ++j) bh[j] = nbh[j];
+            }
         }
         // Keep the pack (which waits for this iteration's global loads) after
         // the MFMAs: the compiler may otherwise hoist the LDS writes above
