@@ -243,11 +243,13 @@ int mg_tuned_config(int path, int64_t M, int64_t N, int64_t K);
  * and argument rules of mg_sgemm (quick returns included); problems must not
  * write overlapping C.  Every problem is tiled with its own tile shape (chosen
  * by the tuning table, else by its size), and one grid that fills the GPU
- * walks the tiles of all problems, largest tiles first.
+ * takes the tiles of all problems, largest first, each workgroup taking the
+ * next tile when it finishes one.
  * workspace: device memory of at least mg_gemm_batched_workspace_size bytes,
- * 256-byte aligned; it receives the problem descriptors (one host-to-device
- * copy on `stream`, which may block the host until earlier work on the
- * stream is done).
+ * 256-byte aligned; it receives the problem descriptors and the work counter
+ * (one host-to-device copy on `stream`, which may block the host until
+ * earlier work on the stream is done).  Calls that overlap in time must not
+ * share a workspace.
  * Errors: -2 count < 0, -3 problems NULL; an invalid problem i returns its
  * mg_sgemm code (-1 ... -13) and stores i in *bad_problem (if not NULL);
  * MG_ERR_WORKSPACE; MG_ERR_UNSUPPORTED for MG_PATH_FP8_T128.

@@ -3,9 +3,11 @@
 // Every problem of the batch is cut into output tiles of its own variant
 // (tile shape chosen per problem by the tuning table or the default rule),
 // the tiles of all problems form one work list, and a grid sized to fill the
-// GPU once walks that list with a fixed stride.  The host orders the problems
-// by the cost of one of their tiles, largest first, so the stride hands out
-// the long tiles first (longest-processing-time-first scheduling).
+// GPU once takes the items from that list one at a time through an atomic
+// counter: whichever workgroup finishes first takes the next item.  The host
+// orders the problems by the cost of one of their tiles, largest first, so
+// this is greedy longest-processing-time-first scheduling, and the short
+// tiles at the end fill the gaps the long ones leave.
 //
 // Each tile runs the same layered tile code as the single-GEMM kernels
 // (tile_f32.h, tile_bf16.h): the blocked, packed, MFMA micro-kernel scheme of
@@ -47,11 +49,28 @@ MG_DEVICE void f32_variant(const BatchProblem& p, int tm, int tn, float* smem)
 
 // Two waves per SIMD: the register budget stays at 256 per lane, so two
 // workgroups share a CU and one's epilogue overlaps the other's K loop.
+// The next work item for the whole workgroup: thread 0 takes it from the
+// counter and hands it to the others through the first 8 bytes of the panel
+// buffer.  That buffer is free here: every tile ends its K loop with a
+// workgroup barrier after its last LDS access (its epilogue touches no LDS),
+// and the second barrier keeps the next tile's packing from overwriting the
+// slot before every thread has read it.  (A separate __shared__ word would
+// push the bf16x3 kernel's LDS past half a CU and halve its occupancy.)
+MG_DEVICE int64_t next_item(unsigned long long* counter, void* smem)
+{
+    int64_t* slot = static_cast<int64_t*>(smem);
+    if (threadIdx.x == 0) *slot = int64_t(atomicAdd(counter, 1ull));
+    __syncthreads();
+    const int64_t item = *slot;
+    __syncthreads();
+    return item;
+}
+
 __global__ __launch_bounds__(256, 2) void sgemm_batched_kernel(const BatchProblem* __restrict__ P, int count,
-                                                             int64_t total_tiles)
+                                                             int64_t total_tiles, unsigned long long* counter)
 {
     __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<128, 128, 32>()];
-    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+    for (int64_t item = next_item(counter, smem); item < total_tiles; item = next_item(counter, smem)) {
         const BatchProblem& p = P[owner(P, count, item)];
         const int64_t local = item - p.tile_begin;
         const int tm = int(local / p.g.tiles_n), tn = int(local % p.g.tiles_n);
@@ -74,10 +93,10 @@ MG_DEVICE void bf16_variant(const BatchProblem& p, int tm, int tn, uint16_t* sme
 
 template <int TERMS>
 __global__ __launch_bounds__(256, 2) void bf16_batched_kernel(const BatchProblem* __restrict__ P, int count,
-                                                            int64_t total_tiles)
+                                                            int64_t total_tiles, unsigned long long* counter)
 {
     __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<128, 128, 32, TERMS>()];
-    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+    for (int64_t item = next_item(counter, smem); item < total_tiles; item = next_item(counter, smem)) {
         const BatchProblem& p = P[owner(P, count, item)];
         const int64_t local = item - p.tile_begin;
         const int tm = int(local / p.g.tiles_n), tn = int(local % p.g.tiles_n);
@@ -111,13 +130,14 @@ int batched_blocks_per_cu(int path)
 }
 
 hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int count,
-                               int64_t total_tiles, int grid, hipStream_t stream)
+                               int64_t total_tiles, int grid, unsigned long long* counter, hipStream_t stream)
 {
+    const dim3 g(grid), b(256);
     switch (path) {
-    case 0: hipLaunchKernelGGL(sgemm_batched_kernel, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
-    case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
-    case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
-    case 4: hipLaunchKernelGGL(bf16_batched_kernel<16>, dim3(grid), dim3(256), 0, stream, dev_problems, count, total_tiles); break;
+    case 0: hipLaunchKernelGGL(sgemm_batched_kernel, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
+    case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
+    case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
+    case 4: hipLaunchKernelGGL(bf16_batched_kernel<16>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -433,9 +433,14 @@ int device_cus()
     return cus[dev];
 }
 
+// Batched workspace: a 256-byte header holding the work-list counter, then
+// the problem descriptors.  Both travel in one host-to-device copy, which also
+// resets the counter to 0 for every launch.
+constexpr size_t kBatchedHeader = 256;
+
 size_t batched_workspace(int64_t count)
 {
-    return count > 0 ? size_t(count) * sizeof(mg::BatchProblem) : 0;
+    return count > 0 ? kBatchedHeader + size_t(count) * sizeof(mg::BatchProblem) : 0;
 }
 
 // ---- SYR2K: square tile configuration and split of each tile's K loop.
@@ -919,13 +924,16 @@ int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* w
         total += int64_t(b.g.tiles_m) * b.g.tiles_n;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size() * sizeof(mg::BatchProblem),
-                                  hipMemcpyHostToDevice, s);
+    std::vector<uint8_t> upload(kBatchedHeader + host.size() * sizeof(mg::BatchProblem), 0);
+    std::memcpy(upload.data() + kBatchedHeader, host.data(), host.size() * sizeof(mg::BatchProblem));
+    hipError_t e = hipMemcpyAsync(workspace, upload.data(), upload.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_status(e);
     const int64_t slots = int64_t(device_cus()) * mg::batched_blocks_per_cu(path);
     const int grid = int(std::min<int64_t>(total, slots));
-    return hip_status(mg::launch_gemm_batched(path, static_cast<const mg::BatchProblem*>(workspace),
-                                              int(host.size()), total, grid, s));
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    return hip_status(mg::launch_gemm_batched(path, reinterpret_cast<const mg::BatchProblem*>(base + kBatchedHeader),
+                                              int(host.size()), total, grid,
+                                              reinterpret_cast<unsigned long long*>(base), s));
 }
 
 const char* mg_status_string(int status)
