@@ -106,11 +106,17 @@ hipError_t launch_i8_pack(bool trans, const int8_t* X, int64_t ldx, int64_t R, i
     return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN>
+// INTERLEAVE: two register staging sets, so the panel packed during panel
+// kt (panel kt+1) was fetched a whole panel earlier and its LDS writes can be
+// spread between panel kt's matrix instructions instead of forming a burst
+// before the barrier; otherwise the next panel's fetch is issued at the top of
+// a panel and packed after its MFMAs.
+template <int BM, int BN, int WM, int WN, bool INTERLEAVE>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void gemm_i8_kernel(I8Args g)
 {
     constexpr int BK = 128;
+    constexpr int STEPS = BK / 32;
     constexpr int LDR = BK + 16;            // bytes per packed LDS row (padded)
     constexpr int WAVES_N = BN / WN;
     constexpr int NT = (BM / WM) * WAVES_N * 64;
@@ -130,9 +136,6 @@ void gemm_i8_kernel(I8Args g)
     const uint8_t* qA = reinterpret_cast<const uint8_t*>(g.qA);
     const uint8_t* qB = reinterpret_cast<const uint8_t*>(g.qB);
 
-    BytePanel<BM, NT, LDR> pa;
-    BytePanel<BN, NT, LDR> pb;
-
     intx16 acc[V][H];
 #pragma unroll
     for (int i = 0; i < V; ++i)
@@ -141,45 +144,88 @@ void gemm_i8_kernel(I8Args g)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
-    const int nk = int(g.Kp / BK);
-    pa.load(qA, g.ldq, m0, 0, tid);
-    pb.load(qB, g.ldq, n0, 0, tid);
-    pa.store(As[0], tid);
-    pb.store(Bs[0], tid);
-    __syncthreads();
-
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        // One basic block per panel with the next panel's fetch issued before
-        // the MFMAs (the last panel re-fetches itself and packs into the
-        // buffer nobody reads any more).
-        const int kn = kt + 1 < nk ? kt + 1 : kt;
-        pa.load(qA, g.ldq, m0, int64_t(kn) * BK, tid);
-        pb.load(qB, g.ldq, n0, int64_t(kn) * BK, tid);
-        __builtin_amdgcn_sched_barrier(0);
-
+    using PA = BytePanel<BM, NT, LDR>;
+    using PB = BytePanel<BN, NT, LDR>;
+    // Step s of the panel in LDS buffer `cur`; after it, the chunks of the
+    // staged panel (if any) that fall to this step are written to LDS `dst`.
+    auto step = [&](int cur, int s, const PA* sa, const PB* sb, int dst) {
+        const int koff = 32 * s + 16 * h;
+        intx4 a[V], b[H];
 #pragma unroll
-        for (int s = 0; s < BK / 32; ++s) {
-            const int koff = 32 * s + 16 * h;
-            intx4 a[V], b[H];
+        for (int i = 0; i < V; ++i)
+            a[i] = *reinterpret_cast<const intx4*>(&As[cur][(wm0 + 32 * i + c) * LDR + koff]);
 #pragma unroll
-            for (int i = 0; i < V; ++i)
-                a[i] = *reinterpret_cast<const intx4*>(&As[cur][(wm0 + 32 * i + c) * LDR + koff]);
+        for (int j = 0; j < H; ++j)
+            b[j] = *reinterpret_cast<const intx4*>(&Bs[cur][(wn0 + 32 * j + c) * LDR + koff]);
+#pragma unroll
+        for (int i = 0; i < V; ++i)
 #pragma unroll
             for (int j = 0; j < H; ++j)
-                b[j] = *reinterpret_cast<const intx4*>(&Bs[cur][(wn0 + 32 * j + c) * LDR + koff]);
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (sa) {
 #pragma unroll
-            for (int i = 0; i < V; ++i)
+            for (int q = s; q < PA::PER; q += STEPS) sa->store_chunk(As[dst], tid, q);
 #pragma unroll
-                for (int j = 0; j < H; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int q = s; q < PB::PER; q += STEPS) sb->store_chunk(Bs[dst], tid, q);
         }
+    };
 
-        // keep the pack, which waits for the loads above, after the MFMAs
-        __builtin_amdgcn_sched_barrier(0);
-        pa.store(As[cur ^ 1], tid);
-        pb.store(Bs[cur ^ 1], tid);
+    const int nk = int(g.Kp / BK);
+    if constexpr (!INTERLEAVE) {
+        PA pa;
+        PB pb;
+        pa.load(qA, g.ldq, m0, 0, tid);
+        pb.load(qB, g.ldq, n0, 0, tid);
+        pa.store(As[0], tid);
+        pb.store(Bs[0], tid);
         __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            // One basic block per panel with the next panel's fetch issued
+            // before the MFMAs (the last panel re-fetches itself and packs
+            // into the buffer nobody reads any more).
+            const int kn = kt + 1 < nk ? kt + 1 : kt;
+            pa.load(qA, g.ldq, m0, int64_t(kn) * BK, tid);
+            pb.load(qB, g.ldq, n0, int64_t(kn) * BK, tid);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) step(cur, s, nullptr, nullptr, 0);
+            // keep the pack, which waits for the loads above, after the MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+            pa.store(As[cur ^ 1], tid);
+            pb.store(Bs[cur ^ 1], tid);
+            __syncthreads();
+        }
+    } else {
+        // staging set 0 / 1 holds the panel bound for LDS buffer 0 / 1
+        PA pa0, pa1;
+        PB pb0, pb1;
+        pa0.load(qA, g.ldq, m0, 0, tid);
+        pb0.load(qB, g.ldq, n0, 0, tid);
+        const int k1 = nk > 1 ? 1 : 0;
+        pa1.load(qA, g.ldq, m0, int64_t(k1) * BK, tid);
+        pb1.load(qB, g.ldq, n0, int64_t(k1) * BK, tid);
+        pa0.store(As[0], tid);
+        pb0.store(Bs[0], tid);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            {   // panel kt in LDS 0; panel kt+1 in staging 1 goes to LDS 1
+                const int kn = kt + 2 < nk ? kt + 2 : nk - 1;
+                pa0.load(qA, g.ldq, m0, int64_t(kn) * BK, tid);
+                pb0.load(qB, g.ldq, n0, int64_t(kn) * BK, tid);
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s) step(0, s, &pa1, &pb1, 1);
+                __syncthreads();
+            }
+            if (kt + 1 < nk) {   // panel kt+1 in LDS 1; panel kt+2 in staging 0 goes to LDS 0
+                const int kn = kt + 3 < nk ? kt + 3 : nk - 1;
+                pa1.load(qA, g.ldq, m0, int64_t(kn) * BK, tid);
+                pb1.load(qB, g.ldq, n0, int64_t(kn) * BK, tid);
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s) step(1, s, &pa0, &pb0, 0);
+                __syncthreads();
+            }
+        }
     }
 
     // C = alpha*acc + beta*C0 modulo 2^32 (unsigned arithmetic wraps).
@@ -227,13 +273,14 @@ hipError_t launch_scale_c_i32(int32_t* C, int64_t M, int64_t N, int64_t ldc, int
     return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool INTERLEAVE>
 static hipError_t launch_i8_cfg(I8Args g, hipStream_t stream)
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_i8_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    hipLaunchKernelGGL((gemm_i8_kernel<BM, BN, WM, WN, INTERLEAVE>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream,
+                       g);
     return hipGetLastError();
 }
 
@@ -242,15 +289,19 @@ const SgemmConfig kI8Configs[] = {
     {0, 256, 256, 128, 128, 64},
     {1, 128, 128, 128, 64, 64},
     {2, 64, 64, 128, 32, 32},
+    {3, 256, 256, 128, 128, 64},   // packs interleaved with the matrix work
+    {4, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
 };
 const int kNumI8Configs = sizeof(kI8Configs) / sizeof(kI8Configs[0]);
 
 hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream)
 {
     switch (cfg) {
-    case 0: return launch_i8_cfg<256, 256, 128, 64>(g, stream);
-    case 1: return launch_i8_cfg<128, 128, 64, 64>(g, stream);
-    case 2: return launch_i8_cfg<64, 64, 32, 32>(g, stream);
+    case 0: return launch_i8_cfg<256, 256, 128, 64, false>(g, stream);
+    case 1: return launch_i8_cfg<128, 128, 64, 64, false>(g, stream);
+    case 2: return launch_i8_cfg<64, 64, 32, 32, false>(g, stream);
+    case 3: return launch_i8_cfg<256, 256, 128, 64, true>(g, stream);
+    case 4: return launch_i8_cfg<128, 128, 64, 64, true>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

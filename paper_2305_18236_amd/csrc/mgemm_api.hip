@@ -158,8 +158,9 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         return 3;
     }
     if (path == MG_CONFIGS_I8) {
-        if (tiles(M, N, 256, 256) >= 256) return 0;
-        if (tiles(M, N, 128, 128) >= 128) return 1;
+        // interleaved-pack forms (3, 4): 2170 vs 1870 TOP/s at 8192^3
+        if (tiles(M, N, 256, 256) >= 256) return 3;
+        if (tiles(M, N, 128, 128) >= 128) return 4;
         return 2;
     }
     // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the

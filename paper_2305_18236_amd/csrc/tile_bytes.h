@@ -29,10 +29,15 @@ struct BytePanel {
     MG_DEVICE void store(uint8_t* lds, int tid) const
     {
 #pragma unroll
-        for (int s = 0; s < PER; ++s) {
-            const int id = tid + s * NT;
-            *reinterpret_cast<uint4*>(&lds[(id / 8) * LDR + 16 * (id % 8)]) = v[s];
-        }
+        for (int s = 0; s < PER; ++s) store_chunk(lds, tid, s);
+    }
+
+    // One of the PER 16-byte chunks, so that a caller can spread the LDS
+    // writes of a panel between its matrix instructions.
+    MG_DEVICE void store_chunk(uint8_t* lds, int tid, int s) const
+    {
+        const int id = tid + s * NT;
+        *reinterpret_cast<uint4*>(&lds[(id / 8) * LDR + 16 * (id % 8)]) = v[s];
     }
 };
 
