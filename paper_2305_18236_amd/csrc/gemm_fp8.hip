@@ -141,11 +141,17 @@ hipError_t launch_fp8_pack(bool trans, const float* X, int64_t ldx, int64_t R, i
     return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN>
+// INTERLEAVE: two register staging sets, so the panel packed during panel
+// kt (panel kt+1) was fetched a whole panel earlier and its LDS writes are
+// spread between panel kt's matrix instructions instead of forming a burst
+// before the barrier (the same scheme as the INT8 kernel); otherwise the next
+// panel's fetch is issued at the top of a panel and packed after its MFMAs.
+template <int BM, int BN, int WM, int WN, bool INTERLEAVE>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void gemm_fp8_kernel(Fp8Args g)
 {
     constexpr int BK = 128;                 // one scale block per K-panel
+    constexpr int STEPS = BK / 64;
     constexpr int LDR = BK + 16;            // bytes per packed LDS row (padded)
     constexpr int WAVES_N = BN / WN;
     constexpr int NT = (BM / WM) * WAVES_N * 64;
@@ -163,8 +169,8 @@ void gemm_fp8_kernel(Fp8Args g)
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
-    BytePanel<BM, NT, LDR> pa;
-    BytePanel<BN, NT, LDR> pb;
+    using PA = BytePanel<BM, NT, LDR>;
+    using PB = BytePanel<BN, NT, LDR>;
 
     floatx16 acc[V][H];
 #pragma unroll
@@ -190,62 +196,114 @@ void gemm_fp8_kernel(Fp8Args g)
     for (int i = 0; i < V; ++i) sa[i] = g.sA[srow_a[i]];
 #pragma unroll
     for (int j = 0; j < H; ++j) sb[j] = g.sB[srow_b[j]];
-    pa.load(g.qA, g.ldq, m0, 0, tid);
-    pb.load(g.qB, g.ldq, n0, 0, tid);
-    pa.store(As[0], tid);
-    pb.store(Bs[0], tid);
-    __syncthreads();
 
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        // Everything in one basic block, with the fetch of the next panel and
-        // its scale bytes issued before the MFMAs: the last panel re-fetches
-        // itself (inside the packed operands) and packs into the buffer nobody
-        // reads any more.
-        const int kn = kt + 1 < nk ? kt + 1 : kt;
-        pa.load(g.qA, g.ldq, m0, int64_t(kn) * BK, tid);
-        pb.load(g.qB, g.ldq, n0, int64_t(kn) * BK, tid);
+    auto next_scales = [&](int kn) {
 #pragma unroll
         for (int i = 0; i < V; ++i) sa_n[i] = g.sA[srow_a[i] + kn];
 #pragma unroll
         for (int j = 0; j < H; ++j) sb_n[j] = g.sB[srow_b[j] + kn];
-        __builtin_amdgcn_sched_barrier(0);
-
-#pragma unroll
-        for (int s = 0; s < BK / 64; ++s) {
-            const int koff = 64 * s + 32 * h;
-            intx8 a[V], b[H];
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-                const uint8_t* p = &As[cur][(wm0 + 32 * i + c) * LDR + koff];
-                const uint4 lo = *reinterpret_cast<const uint4*>(p);
-                const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
-                a[i] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
-            }
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const uint8_t* p = &Bs[cur][(wn0 + 32 * j + c) * LDR + koff];
-                const uint4 lo = *reinterpret_cast<const uint4*>(p);
-                const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
-                b[j] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
-            }
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
-        }
-
-        // keep the pack, which waits for the loads above, after the MFMAs
-        __builtin_amdgcn_sched_barrier(0);
-        pa.store(As[cur ^ 1], tid);
-        pb.store(Bs[cur ^ 1], tid);
+    };
+    auto take_scales = [&]() {
 #pragma unroll
         for (int i = 0; i < V; ++i) sa[i] = sa_n[i];
 #pragma unroll
         for (int j = 0; j < H; ++j) sb[j] = sb_n[j];
+    };
+    // Step s of the panel in LDS buffer `cur`; after it, the chunks of the
+    // staged panel (if any) that fall to this step are written to LDS `dst`.
+    auto step = [&](int cur, int s, const PA* stage_a, const PB* stage_b, int dst) {
+        const int koff = 64 * s + 32 * h;
+        intx8 a[V], b[H];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const uint8_t* p = &As[cur][(wm0 + 32 * i + c) * LDR + koff];
+            const uint4 lo = *reinterpret_cast<const uint4*>(p);
+            const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+            a[i] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const uint8_t* p = &Bs[cur][(wn0 + 32 * j + c) * LDR + koff];
+            const uint4 lo = *reinterpret_cast<const uint4*>(p);
+            const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+            b[j] = intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
+        if (stage_a) {
+#pragma unroll
+            for (int q = s; q < PA::PER; q += STEPS) stage_a->store_chunk(As[dst], tid, q);
+#pragma unroll
+            for (int q = s; q < PB::PER; q += STEPS) stage_b->store_chunk(Bs[dst], tid, q);
+        }
+    };
+
+    if constexpr (!INTERLEAVE) {
+        PA pa;
+        PB pb;
+        pa.load(g.qA, g.ldq, m0, 0, tid);
+        pb.load(g.qB, g.ldq, n0, 0, tid);
+        pa.store(As[0], tid);
+        pb.store(Bs[0], tid);
         __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            // Everything in one basic block, with the fetch of the next panel
+            // and its scale bytes issued before the MFMAs: the last panel
+            // re-fetches itself (inside the packed operands) and packs into
+            // the buffer nobody reads any more.
+            const int kn = kt + 1 < nk ? kt + 1 : kt;
+            pa.load(g.qA, g.ldq, m0, int64_t(kn) * BK, tid);
+            pb.load(g.qB, g.ldq, n0, int64_t(kn) * BK, tid);
+            next_scales(kn);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) step(cur, s, nullptr, nullptr, 0);
+            // keep the pack, which waits for the loads above, after the MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+            pa.store(As[cur ^ 1], tid);
+            pb.store(Bs[cur ^ 1], tid);
+            take_scales();
+            __syncthreads();
+        }
+    } else {
+        // staging set 0 / 1 holds the panel bound for LDS buffer 0 / 1
+        PA pa0, pa1;
+        PB pb0, pb1;
+        pa0.load(g.qA, g.ldq, m0, 0, tid);
+        pb0.load(g.qB, g.ldq, n0, 0, tid);
+        const int k1 = nk > 1 ? 1 : 0;
+        pa1.load(g.qA, g.ldq, m0, int64_t(k1) * BK, tid);
+        pb1.load(g.qB, g.ldq, n0, int64_t(k1) * BK, tid);
+        pa0.store(As[0], tid);
+        pb0.store(Bs[0], tid);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            {   // panel kt in LDS 0; panel kt+1 in staging 1 goes to LDS 1
+                const int kn = kt + 2 < nk ? kt + 2 : nk - 1;
+                pa0.load(g.qA, g.ldq, m0, int64_t(kn) * BK, tid);
+                pb0.load(g.qB, g.ldq, n0, int64_t(kn) * BK, tid);
+                next_scales(kt + 1 < nk ? kt + 1 : kt);
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s) step(0, s, &pa1, &pb1, 1);
+                take_scales();
+                __syncthreads();
+            }
+            if (kt + 1 < nk) {   // panel kt+1 in LDS 1; panel kt+2 in staging 0 goes to LDS 0
+                const int kn = kt + 3 < nk ? kt + 3 : nk - 1;
+                pa1.load(g.qA, g.ldq, m0, int64_t(kn) * BK, tid);
+                pb1.load(g.qB, g.ldq, n0, int64_t(kn) * BK, tid);
+                next_scales(kt + 2 < nk ? kt + 2 : kt + 1);
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s) step(1, s, &pa0, &pb0, 0);
+                take_scales();
+                __syncthreads();
+            }
+        }
     }
 
     const float alpha = g.alpha, beta = g.beta;
@@ -269,13 +327,14 @@ void gemm_fp8_kernel(Fp8Args g)
     }
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool INTERLEAVE>
 static hipError_t launch_fp8_cfg(Fp8Args g, hipStream_t stream)
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_fp8_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    hipLaunchKernelGGL((gemm_fp8_kernel<BM, BN, WM, WN, INTERLEAVE>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0,
+                       stream, g);
     return hipGetLastError();
 }
 
@@ -286,17 +345,21 @@ const SgemmConfig kFp8Configs[] = {
     {2, 128, 128, 128, 64, 64},
     {3, 64, 64, 128, 32, 32},
     {4, 256, 256, 128, 128, 64},
+    {5, 256, 256, 128, 128, 64},   // packs interleaved with the matrix work
+    {6, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
 };
 const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
 
 hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
 {
     switch (cfg) {
-    case 0: return launch_fp8_cfg<256, 256, 128, 128>(g, stream);
-    case 1: return launch_fp8_cfg<256, 128, 128, 64>(g, stream);
-    case 2: return launch_fp8_cfg<128, 128, 64, 64>(g, stream);
-    case 3: return launch_fp8_cfg<64, 64, 32, 32>(g, stream);
-    case 4: return launch_fp8_cfg<256, 256, 128, 64>(g, stream);
+    case 0: return launch_fp8_cfg<256, 256, 128, 128, false>(g, stream);
+    case 1: return launch_fp8_cfg<256, 128, 128, 64, false>(g, stream);
+    case 2: return launch_fp8_cfg<128, 128, 64, 64, false>(g, stream);
+    case 3: return launch_fp8_cfg<64, 64, 32, 32, false>(g, stream);
+    case 4: return launch_fp8_cfg<256, 256, 128, 64, false>(g, stream);
+    case 5: return launch_fp8_cfg<256, 256, 128, 64, true>(g, stream);
+    case 6: return launch_fp8_cfg<128, 128, 64, 64, true>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

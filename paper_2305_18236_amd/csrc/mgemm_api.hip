@@ -153,8 +153,9 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
     const int64_t cus = device_cus();
     if (path == MG_PATH_FP8_T128) {
-        if (tiles(M, N, 256, 256) >= 256) return 4;
-        if (tiles(M, N, 128, 128) >= 128) return 2;
+        // interleaved-pack forms (5, 6): 2300 vs 1970 TFLOP/s at 8192^3
+        if (tiles(M, N, 256, 256) >= 256) return 5;
+        if (tiles(M, N, 128, 128) >= 128) return 6;
         return 3;
     }
     if (path == MG_CONFIGS_I8) {

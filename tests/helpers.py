@@ -15,11 +15,17 @@ TOL = {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp8": 6e-2, "fp16": 2e-3}
 # bar is statistical: it needs enough sign-random terms to average out, so
 # below K = 32 the worst-case bound applies instead.
 BF16X3_WORST = 5e-5
+# FP8: each factor is rounded to 3 mantissa bits (relative error <= 2^-4), so
+# one product can be off by (2*2^-4 + 2^-8) |a||b|; the 6e-2 bar needs sums
+# of enough sign-random terms, and below K = 32 the worst case applies.
+FP8_WORST = 0.13
 
 
 def tolerance(path: str, K: int) -> float:
     if path == "bf16x3" and K < 32:
         return BF16X3_WORST
+    if path == "fp8" and K < 32:
+        return FP8_WORST
     return TOL[path]
 
 
