@@ -257,13 +257,18 @@ struct BfPackedPanel {
     MG_DEVICE void store(uint16_t* hi_lds, uint16_t* lo_lds, int tid) const
     {
 #pragma unroll
-        for (int s = 0; s < PER; ++s) {
-            const int q = tid + s * NT;
-            if (CHUNKS % NT != 0 && q >= CHUNKS) break;
-            const int r = row_perm(q / CPR), c = (q % CPR) * 8;
-            *reinterpret_cast<uint4*>(hi_lds + r * LDR + c) = v[0][s];
-            if (TERMS == 3) *reinterpret_cast<uint4*>(lo_lds + r * LDR + c) = v[NL - 1][s];
-        }
+        for (int s = 0; s < PER; ++s) store_chunk(hi_lds, lo_lds, tid, s);
+    }
+
+    // One of the PER chunks, so that a caller can spread a panel's LDS writes
+    // between its matrix instructions.
+    MG_DEVICE void store_chunk(uint16_t* hi_lds, uint16_t* lo_lds, int tid, int s) const
+    {
+        const int q = tid + s * NT;
+        if (CHUNKS % NT != 0 && q >= CHUNKS) return;
+        const int r = row_perm(q / CPR), c = (q % CPR) * 8;
+        *reinterpret_cast<uint4*>(hi_lds + r * LDR + c) = v[0][s];
+        if (TERMS == 3) *reinterpret_cast<uint4*>(lo_lds + r * LDR + c) = v[NL - 1][s];
     }
 };
 
@@ -330,87 +335,75 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int nk = int((g.K + BK - 1) / BK);
-    if (nk > 0) {
-        fetch(0);
-        pack(0);
-    }
-    __syncthreads();
-
     constexpr int STEPS = BK / 16;          // MFMA k-steps per panel
-    // Where the next panel is converted and packed: after the last MFMA step
-    // (PACK_AT == STEPS).  Packing half-way through the panel was measured
-    // slower here: the conversion's registers then overlap the fragments'.
-    constexpr int PACK_AT = STEPS;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
 
-        // Fragment reads of one MFMA k-step.  bf16x3 issues B before A and
-        // the lo halves before the hi ones, in the order its three MFMA groups
-        // consume them (lo(A)*hi(B), hi(A)*lo(B), hi(A)*hi(B)), so the first
-        // group starts while the later fragments are still in flight.  The
-        // single-term kinds, with half the fragment registers, read the next
-        // step's fragments before issuing this step's MFMAs (software
-        // pipelining across the panel's steps).
-        auto read_step = [&](int s, bf16x8 (&xah)[V], bf16x8 (&xal)[V], bf16x8 (&xbh)[H], bf16x8 (&xbl)[H]) {
-            const int koff = 16 * s + 8 * h;
+    // Fragment reads of one MFMA k-step from LDS buffer `cur`.  bf16x3 issues
+    // B before A and the lo halves before the hi ones, in the order its three
+    // MFMA groups consume them (lo(A)*hi(B), hi(A)*lo(B), hi(A)*hi(B)), so the
+    // first group starts while the later fragments are still in flight.  The
+    // single-term kinds, with half the fragment registers, read the next
+    // step's fragments before issuing this step's MFMAs (software pipelining
+    // across the panel's steps).
+    auto read_step = [&](int cur, int s, bf16x8 (&xah)[V], bf16x8 (&xal)[V], bf16x8 (&xbh)[H],
+                         bf16x8 (&xbl)[H]) {
+        const int koff = 16 * s + 8 * h;
 #pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const int off = (wn0 + 32 * j + c) * LDR + koff;
-                xbh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
-            }
-            if constexpr (TERMS == 3) {
-#pragma unroll
-                for (int i = 0; i < V; ++i) {
-                    const int off = (wm0 + 32 * i + c) * LDR + koff;
-                    xal[i] = *reinterpret_cast<const bf16x8*>(&As[cur][NL - 1][off]);
-                }
-#pragma unroll
-                for (int j = 0; j < H; ++j) {
-                    const int off = (wn0 + 32 * j + c) * LDR + koff;
-                    xbl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
-                }
-            }
+        for (int j = 0; j < H; ++j) {
+            const int off = (wn0 + 32 * j + c) * LDR + koff;
+            xbh[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][0][off]);
+        }
+        if constexpr (TERMS == 3) {
 #pragma unroll
             for (int i = 0; i < V; ++i) {
                 const int off = (wm0 + 32 * i + c) * LDR + koff;
-                xah[i] = *reinterpret_cast<const bf16x8*>(&As[cur][0][off]);
+                xal[i] = *reinterpret_cast<const bf16x8*>(&As[cur][NL - 1][off]);
             }
-        };
-        constexpr bool PIPE = TERMS != 3;
-        bf16x8 ah[V], bh[H], al[V], bl[H];
-        if (PIPE) read_step(0, ah, al, bh, bl);
 #pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            bf16x8 nah[V], nbh[H], nal[V], nbl[H];
-            if (!PIPE) read_step(s, ah, al, bh, bl);
-            else if (s + 1 < STEPS) read_step(s + 1, nah, nal, nbh, nbl);
-            if (s == PACK_AT) {
-                // Convert and pack the panel fetched at the top of this
-                // iteration into the other LDS buffer (last read before the
-                // previous barrier), between two MFMA groups so that its
-                // VALU work can run beside the matrix core.  On the last
-                // panel this rewrites stale data nobody reads.
-                pack(cur ^ 1);
+            for (int j = 0; j < H; ++j) {
+                const int off = (wn0 + 32 * j + c) * LDR + koff;
+                xbl[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][NL - 1][off]);
             }
-            if (TERMS == 3) {
-                // small terms first; consecutive instructions use different accumulators
+        }
 #pragma unroll
-                for (int i = 0; i < V; ++i)
-#pragma unroll
-                    for (int j = 0; j < H; ++j)
-                        acc[i][j] = mfma16<TERMS>(al[i], bh[j], acc[i][j]);
-#pragma unroll
-                for (int i = 0; i < V; ++i)
-#pragma unroll
-                    for (int j = 0; j < H; ++j)
-                        acc[i][j] = mfma16<TERMS>(ah[i], bl[j], acc[i][j]);
-            }
+        for (int i = 0; i < V; ++i) {
+            const int off = (wm0 + 32 * i + c) * LDR + koff;
+            xah[i] = *reinterpret_cast<const bf16x8*>(&As[cur][0][off]);
+        }
+    };
+    auto mfma_step = [&](const bf16x8 (&ah)[V], const bf16x8 (&al)[V], const bf16x8 (&bh)[H],
+                         const bf16x8 (&bl)[H]) {
+        if (TERMS == 3) {
+            // small terms first; consecutive instructions use different accumulators
 #pragma unroll
             for (int i = 0; i < V; ++i)
 #pragma unroll
                 for (int j = 0; j < H; ++j)
-                    acc[i][j] = mfma16<TERMS>(ah[i], bh[j], acc[i][j]);
+                    acc[i][j] = mfma16<TERMS>(al[i], bh[j], acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = mfma16<TERMS>(ah[i], bl[j], acc[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+                acc[i][j] = mfma16<TERMS>(ah[i], bh[j], acc[i][j]);
+    };
+    constexpr bool PIPE = TERMS != 3;
+    // The MFMA work of the panel in LDS buffer `cur`; `after_step(s)` runs
+    // after step s's matrix instructions are issued.
+    auto panel = [&](int cur, auto&& after_step) {
+        bf16x8 ah[V], bh[H], al[V], bl[H];
+        if (PIPE) read_step(cur, 0, ah, al, bh, bl);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            bf16x8 nah[V], nbh[H], nal[V], nbl[H];
+            if (!PIPE) read_step(cur, s, ah, al, bh, bl);
+            else if (s + 1 < STEPS) read_step(cur, s + 1, nah, nal, nbh, nbl);
+            mfma_step(ah, al, bh, bl);
+            after_step(s);
             if (PIPE && s + 1 < STEPS) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) ah[i] = nah[i];
@@ -418,12 +411,74 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
                 for (int j = 0; j < H; ++j) bh[j] = nbh[j];
             }
         }
-        // Keep the pack (which waits for this iteration's global loads) after
-        // the MFMAs: the compiler may otherwise hoist the LDS writes above
-        // them, since they target the other buffer.
-        __builtin_amdgcn_sched_barrier(0);
-        if (PACK_AT == STEPS) pack(cur ^ 1);   // the last panel rewrites stale data nobody reads
+    };
+
+    if constexpr (PACKED && TERMS != 3 && WM * WN < 128 * 128) {
+        // Pre-packed single-term operands: two register staging sets, so the
+        // panel packed during panel kt (panel kt+1) was fetched a whole panel
+        // earlier and its LDS writes are spread between panel kt's matrix
+        // instructions instead of forming a burst before the barrier.  (Not
+        // with 128 x 128 wave tiles, whose accumulators leave no room for the
+        // second set.)
+        using PA = typename BfLoaderSel<PACKED, BM, BK, LDR, NT, !TA, TERMS>::type;
+        using PB = typename BfLoaderSel<PACKED, BN, BK, LDR, NT, TB, TERMS>::type;
+        PA pa0, pa1;
+        PB pb0, pb1;
+        const uint16_t* qa = reinterpret_cast<const uint16_t*>(g.A);
+        const uint16_t* qb = reinterpret_cast<const uint16_t*>(g.B);
+        auto load = [&](PA& xa, PB& xb, int kp) {
+            xa.load(qa, g.plane_a, g.lda, m0, int64_t(kp) * BK, tid);
+            xb.load(qb, g.plane_b, g.ldb, n0, int64_t(kp) * BK, tid);
+        };
+        if (nk > 0) {
+            load(pa0, pb0, 0);
+            load(pa1, pb1, nk > 1 ? 1 : 0);
+            pa0.store(As[0][0], As[0][NL - 1], tid);
+            pb0.store(Bs[0][0], Bs[0][NL - 1], tid);
+        }
         __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            // panel kt in LDS 0; panel kt+1 (staging 1) goes to LDS 1
+            load(pa0, pb0, kt + 2 < nk ? kt + 2 : nk - 1);
+            panel(0, [&](int s) {
+#pragma unroll
+                for (int q = s; q < PA::PER; q += STEPS) pa1.store_chunk(As[1][0], As[1][NL - 1], tid, q);
+#pragma unroll
+                for (int q = s; q < PB::PER; q += STEPS) pb1.store_chunk(Bs[1][0], Bs[1][NL - 1], tid, q);
+            });
+            __syncthreads();
+            if (kt + 1 < nk) {
+                // panel kt+1 in LDS 1; panel kt+2 (staging 0) goes to LDS 0
+                load(pa1, pb1, kt + 3 < nk ? kt + 3 : nk - 1);
+                panel(1, [&](int s) {
+#pragma unroll
+                    for (int q = s; q < PA::PER; q += STEPS) pa0.store_chunk(As[0][0], As[0][NL - 1], tid, q);
+#pragma unroll
+                    for (int q = s; q < PB::PER; q += STEPS) pb0.store_chunk(Bs[0][0], Bs[0][NL - 1], tid, q);
+                });
+                __syncthreads();
+            }
+        }
+    } else {
+        if (nk > 0) {
+            fetch(0);
+            pack(0);
+        }
+        __syncthreads();
+        // The next panel is converted and packed after the last MFMA step:
+        // packing half-way through the panel was measured slower here (the
+        // conversion's registers then overlap the fragments').
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) fetch(int64_t(kt + 1) * BK);
+            panel(cur, [](int) {});
+            // Keep the pack (which waits for this iteration's global loads)
+            // after the MFMAs: the compiler may otherwise hoist the LDS writes
+            // above them, since they target the other buffer.
+            __builtin_amdgcn_sched_barrier(0);
+            pack(cur ^ 1);   // the last panel rewrites stale data nobody reads
+            __syncthreads();
+        }
     }
 
     // Epilogue: C = alpha*acc + beta*C0 (C0 not read when beta == 0).
