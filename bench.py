@@ -304,11 +304,34 @@ def bench_batched(args, torch, si, native, dev):
             res[name] = {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
                          "launches": 1 if name == "persistent" else len(ops)}
         res["speedup_persistent_vs_per_problem"] = round(res["per_problem"]["ms"] / res["persistent"]["ms"], 3)
+        res["persistent"].update(_batched_tail(native, torch, pid, arr, len(ops), ws, need, sp, dev))
         out["paths"][path] = res
     out["value"] = out["paths"]["fp32"]["persistent"]["tflops"]
     out["ms_per_step"] = out["paths"]["fp32"]["persistent"]["ms"]
     out["dtype"] = "f32"
     print(json.dumps(out), flush=True)
+
+
+def _batched_tail(native, torch, pid, arr, count, ws, need, sp, dev):
+    """One more persistent launch with per-workgroup wall-clock stamps: how
+    long the workgroups that found the work list empty waited for the last
+    tiles.  tail_idle_frac = sum over workgroups of (last end - own end) over
+    workgroups x (last end - first start)."""
+    slots = native.mg_batched_slots(pid)
+    stamps = torch.zeros(2 * slots, dtype=torch.int64, device=dev)
+    st, bad, grid = native.mg_gemm_batched_timed(pid, count, arr, ws.data_ptr(), need, sp, stamps.data_ptr(),
+                                                 2 * slots)
+    native.check(st, "mg_gemm_batched_timed")
+    torch.cuda.synchronize()
+    t = stamps.cpu().view(-1, 2)[:grid].double()
+    hz = float(native.mg_wall_clock_hz())
+    t0, t1 = float(t[:, 0].min()), float(t[:, 1].max())
+    ends = t[:, 1]
+    return {"workgroups": grid,
+            "stamped_span_us": round((t1 - t0) / hz * 1e6, 1),
+            "tail_us": round((t1 - float(ends.min())) / hz * 1e6, 1),
+            "median_end_to_last_us": round((t1 - float(ends.median())) / hz * 1e6, 1),
+            "tail_idle_frac": round(float((t1 - ends).sum()) / (grid * (t1 - t0)), 4)}
 
 
 def bench_chain(args, torch, si, native, dev):

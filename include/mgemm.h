@@ -262,6 +262,29 @@ int mg_gemm_batched(int path, int64_t count, const mg_problem *problems,
                     int64_t *bad_problem);
 
 /*
+ * Timing of the persistent launch, for measuring its tail: the time that
+ * workgroups which found the work list empty wait for the last tiles.
+ * mg_gemm_batched_timed is mg_gemm_batched (same arguments, results and
+ * errors) that also records, for each workgroup b of the launch,
+ * stamps[2b] = the wall clock when it started and stamps[2b + 1] = the wall
+ * clock after its last tile, and stores the number of workgroups in *grid
+ * (if grid is not NULL; 0 when nothing was launched).  stamps: device array
+ * of stamps_len >= 2 * mg_batched_slots(path) words, written asynchronously
+ * on `stream`.  Extra error: -8 stamps NULL or too short.
+ * mg_batched_slots: the most workgroups a persistent launch of this path
+ * uses on the current device (compute units x resident workgroups per unit;
+ * 0 for a path without a batched kernel).
+ * mg_wall_clock_hz: ticks per second of the stamps' clock (constant rate,
+ * independent of the shader clock); -1 if the device cannot be queried.
+ */
+int mg_batched_slots(int path);
+int mg_gemm_batched_timed(int path, int64_t count, const mg_problem *problems,
+                          void *workspace, size_t workspace_bytes, void *stream,
+                          int64_t *bad_problem, unsigned long long *stamps,
+                          int64_t stamps_len, int *grid);
+int64_t mg_wall_clock_hz(void);
+
+/*
  * The pack-stage conversion of the BF16 paths on its own (Table 1's bf16
  * operand type, round to nearest even): hi[t] = bf16(x[t]) and, when lo is
  * not NULL, lo[t] = bf16(x[t] - hi[t]), as raw bf16 bit patterns.  x, hi, lo

@@ -97,6 +97,13 @@ def lib():
     L.mg_gemm_batched.argtypes = [ci, i64, ctypes.POINTER(mg_problem), vp, sz, vp,
                                   ctypes.POINTER(i64)]
     L.mg_gemm_batched.restype = ci
+    L.mg_batched_slots.argtypes = [ci]
+    L.mg_batched_slots.restype = ci
+    L.mg_gemm_batched_timed.argtypes = [ci, i64, ctypes.POINTER(mg_problem), vp, sz, vp, ctypes.POINTER(i64),
+                                        vp, i64, ctypes.POINTER(ci)]
+    L.mg_gemm_batched_timed.restype = ci
+    L.mg_wall_clock_hz.argtypes = []
+    L.mg_wall_clock_hz.restype = i64
     L.mg_status_string.argtypes = [ci]
     L.mg_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -219,6 +226,24 @@ def mg_gemm_batched(path, count, problems, workspace, workspace_bytes, stream):
     st = lib().mg_gemm_batched(int(path), int(count), problems, workspace, workspace_bytes, stream,
                                ctypes.byref(bad))
     return int(st), int(bad.value)
+
+
+def mg_batched_slots(path) -> int:
+    return int(lib().mg_batched_slots(int(path)))
+
+
+def mg_gemm_batched_timed(path, count, problems, workspace, workspace_bytes, stream, stamps, stamps_len):
+    """As mg_gemm_batched, plus per-workgroup start/end wall-clock stamps
+    (device array).  Returns (status, bad_problem index, grid)."""
+    bad = ctypes.c_int64(-1)
+    grid = ctypes.c_int(0)
+    st = lib().mg_gemm_batched_timed(int(path), int(count), problems, workspace, workspace_bytes, stream,
+                                     ctypes.byref(bad), stamps, int(stamps_len), ctypes.byref(grid))
+    return int(st), int(bad.value), int(grid.value)
+
+
+def mg_wall_clock_hz() -> int:
+    return int(lib().mg_wall_clock_hz())
 
 
 def mg_num_configs(path) -> int:

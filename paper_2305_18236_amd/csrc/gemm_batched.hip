@@ -66,10 +66,21 @@ MG_DEVICE int64_t next_item(unsigned long long* counter, void* smem)
     return item;
 }
 
+// Optional timing of the launch: workgroup b writes the constant-rate wall
+// clock at its start to stamps[2b] and after its last item to stamps[2b + 1]
+// (one 8-byte vector store each, from thread 0), so the caller can measure
+// how long workgroups idle at the end while the last tiles finish.
+MG_DEVICE void stamp(unsigned long long* stamps, int which)
+{
+    if (stamps != nullptr && threadIdx.x == 0) stamps[2 * int64_t(blockIdx.x) + which] = wall_clock64();
+}
+
 __global__ __launch_bounds__(256, 2) void sgemm_batched_kernel(const BatchProblem* __restrict__ P, int count,
-                                                             int64_t total_tiles, unsigned long long* counter)
+                                                             int64_t total_tiles, unsigned long long* counter,
+                                                             unsigned long long* stamps)
 {
     __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<128, 128, 32>()];
+    stamp(stamps, 0);
     for (int64_t item = next_item(counter, smem); item < total_tiles; item = next_item(counter, smem)) {
         const BatchProblem& p = P[owner(P, count, item)];
         const int64_t local = item - p.tile_begin;
@@ -77,6 +88,7 @@ __global__ __launch_bounds__(256, 2) void sgemm_batched_kernel(const BatchProble
         if (p.variant == 0) f32_variant<64, 64, 32, 32, 32>(p, tm, tn, smem);
         else f32_variant<128, 128, 32, 64, 64>(p, tm, tn, smem);
     }
+    stamp(stamps, 1);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int TERMS>
@@ -93,9 +105,11 @@ MG_DEVICE void bf16_variant(const BatchProblem& p, int tm, int tn, uint16_t* sme
 
 template <int TERMS>
 __global__ __launch_bounds__(256, 2) void bf16_batched_kernel(const BatchProblem* __restrict__ P, int count,
-                                                            int64_t total_tiles, unsigned long long* counter)
+                                                            int64_t total_tiles, unsigned long long* counter,
+                                                            unsigned long long* stamps)
 {
     __shared__ __attribute__((aligned(16))) uint16_t smem[bf16_lds_elems<128, 128, 32, TERMS>()];
+    stamp(stamps, 0);
     for (int64_t item = next_item(counter, smem); item < total_tiles; item = next_item(counter, smem)) {
         const BatchProblem& p = P[owner(P, count, item)];
         const int64_t local = item - p.tile_begin;
@@ -106,6 +120,7 @@ __global__ __launch_bounds__(256, 2) void bf16_batched_kernel(const BatchProblem
         default: bf16_variant<128, 128, 32, 64, 64, TERMS>(p, tm, tn, smem); break;
         }
     }
+    stamp(stamps, 1);
 }
 
 static const void* batched_kernel(int path)
@@ -130,14 +145,15 @@ int batched_blocks_per_cu(int path)
 }
 
 hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int count,
-                               int64_t total_tiles, int grid, unsigned long long* counter, hipStream_t stream)
+                               int64_t total_tiles, int grid, unsigned long long* counter,
+                               unsigned long long* stamps, hipStream_t stream)
 {
     const dim3 g(grid), b(256);
     switch (path) {
-    case 0: hipLaunchKernelGGL(sgemm_batched_kernel, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
-    case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
-    case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
-    case 4: hipLaunchKernelGGL(bf16_batched_kernel<16>, g, b, 0, stream, dev_problems, count, total_tiles, counter); break;
+    case 0: hipLaunchKernelGGL(sgemm_batched_kernel, g, b, 0, stream, dev_problems, count, total_tiles, counter, stamps); break;
+    case 1: hipLaunchKernelGGL(bf16_batched_kernel<3>, g, b, 0, stream, dev_problems, count, total_tiles, counter, stamps); break;
+    case 2: hipLaunchKernelGGL(bf16_batched_kernel<1>, g, b, 0, stream, dev_problems, count, total_tiles, counter, stamps); break;
+    case 4: hipLaunchKernelGGL(bf16_batched_kernel<16>, g, b, 0, stream, dev_problems, count, total_tiles, counter, stamps); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -60,8 +60,11 @@ extern const int kSgemmBatchedCfg[kSgemmBatchedVariants];
 extern const int kBf16BatchedCfg[kBf16BatchedVariants];
 
 // counter: a device word holding 0 at launch (the work-list cursor).
+// stamps: nullptr, or 2 * grid words that receive each workgroup's start and
+// end wall-clock times.
 hipError_t launch_gemm_batched(int path, const BatchProblem* dev_problems, int count,
-                               int64_t total_tiles, int grid, unsigned long long* counter, hipStream_t stream);
+                               int64_t total_tiles, int grid, unsigned long long* counter,
+                               unsigned long long* stamps, hipStream_t stream);
 int batched_blocks_per_cu(int path);
 
 hipError_t launch_scale_c(float* C, int64_t M, int64_t N, int64_t ldc, float beta, hipStream_t stream);

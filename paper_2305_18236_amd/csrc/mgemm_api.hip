@@ -866,9 +866,15 @@ size_t mg_gemm_batched_workspace_size(int path, int64_t count)
     return batched_workspace(count);
 }
 
-int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* workspace,
-                    size_t workspace_bytes, void* stream, int64_t* bad_problem)
+}  // extern "C"
+
+namespace {
+
+// stamps: nullptr, or room for 2 * grid words (checked by the caller).
+int run_batched(int path, int64_t count, const mg_problem* problems, void* workspace, size_t workspace_bytes,
+                void* stream, int64_t* bad_problem, unsigned long long* stamps, int* grid_out)
 {
+    if (grid_out) *grid_out = 0;
     if (!batched_path(path)) return MG_ERR_UNSUPPORTED;
     if (count < 0) return -2;
     if (count > INT_MAX) return MG_ERR_TOO_LARGE;
@@ -933,9 +939,44 @@ int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* w
     const int64_t slots = int64_t(device_cus()) * mg::batched_blocks_per_cu(path);
     const int grid = int(std::min<int64_t>(total, slots));
     uint8_t* base = static_cast<uint8_t*>(workspace);
+    if (grid_out) *grid_out = grid;
     return hip_status(mg::launch_gemm_batched(path, reinterpret_cast<const mg::BatchProblem*>(base + kBatchedHeader),
                                               int(host.size()), total, grid,
-                                              reinterpret_cast<unsigned long long*>(base), s));
+                                              reinterpret_cast<unsigned long long*>(base), stamps, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_gemm_batched(int path, int64_t count, const mg_problem* problems, void* workspace,
+                    size_t workspace_bytes, void* stream, int64_t* bad_problem)
+{
+    return run_batched(path, count, problems, workspace, workspace_bytes, stream, bad_problem, nullptr, nullptr);
+}
+
+int mg_batched_slots(int path)
+{
+    if (!batched_path(path)) return 0;
+    return int(std::min<int64_t>(int64_t(device_cus()) * mg::batched_blocks_per_cu(path), INT_MAX / 2));
+}
+
+int mg_gemm_batched_timed(int path, int64_t count, const mg_problem* problems, void* workspace,
+                          size_t workspace_bytes, void* stream, int64_t* bad_problem,
+                          unsigned long long* stamps, int64_t stamps_len, int* grid)
+{
+    if (grid) *grid = 0;
+    if (!batched_path(path)) return MG_ERR_UNSUPPORTED;
+    if (stamps == nullptr || stamps_len < 2 * int64_t(mg_batched_slots(path))) return -8;
+    return run_batched(path, count, problems, workspace, workspace_bytes, stream, bad_problem, stamps, grid);
+}
+
+int64_t mg_wall_clock_hz(void)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return -1;
+    return int64_t(khz) * 1000;
 }
 
 const char* mg_status_string(int status)

@@ -103,3 +103,56 @@ def test_uneven_512_workload_sampled(gpu, path):
         worst = max(worst, oracle.normalized_error(C[I, J], cref, d))
     print(f"{path}: worst sampled normalised error over 512 problems {worst:.3e}")
     assert worst <= tolerance(path, 32)
+
+
+@pytest.mark.parametrize("path", ["fp32", "bf16x3"])
+def test_timed_launch_matches_and_stamps_are_valid(gpu, path):
+    """mg_gemm_batched_timed computes what mg_gemm_batched computes (bit for
+    bit) and records a start and end wall-clock stamp per workgroup."""
+    from paper_2305_18236_amd import _native
+    pid = PID[path]
+    probs = [p.to_device(gpu) for p in _mixed_batch(13, count=30)]
+    _run_batched(probs, path, gpu)
+    plain = [p.result() for p in probs]
+    for p in probs:
+        p.reset_c()
+    arr = (_native.mg_problem * len(probs))()
+    for i, p in enumerate(probs):
+        arr[i] = _native.mg_problem(p.tA.encode(), p.tB.encode(), p.M, p.N, p.K, p.alpha, p.beta,
+                                    p.dA.data_ptr(), p.lda, p.dB.data_ptr(), p.ldb, p.dC.data_ptr(), p.ldc)
+    need = _native.mg_gemm_batched_workspace_size(pid, len(probs))
+    ws = torch.empty(need, dtype=torch.uint8, device=gpu)
+    slots = _native.mg_batched_slots(pid)
+    assert slots >= 256
+    stamps = torch.zeros(2 * slots, dtype=torch.int64, device=gpu)
+    sp = torch.cuda.current_stream().cuda_stream
+    # stamps missing or too short: rejected on the host, nothing launched
+    assert _native.mg_gemm_batched_timed(pid, len(probs), arr, ws.data_ptr(), need, sp, None, 2 * slots)[0] == -8
+    assert _native.mg_gemm_batched_timed(pid, len(probs), arr, ws.data_ptr(), need, sp, stamps.data_ptr(),
+                                         2 * slots - 1)[0] == -8
+    st, bad, grid = _native.mg_gemm_batched_timed(pid, len(probs), arr, ws.data_ptr(), need, sp,
+                                                  stamps.data_ptr(), 2 * slots)
+    assert st == 0, (_native.status_string(st), bad)
+    for p, Cp in zip(probs, plain):
+        if p.M and p.N:
+            assert np.array_equal(p.result(), Cp), (path, p.M, p.N, p.K)
+    t = stamps.cpu().numpy().reshape(-1, 2)
+    assert 0 < grid <= slots
+    start, end = t[:grid, 0], t[:grid, 1]
+    assert (start > 0).all() and (end >= start).all()
+    assert (t[grid:] == 0).all()              # workgroups beyond the grid do not exist
+    hz = _native.mg_wall_clock_hz()
+    assert hz > 0
+    span = (end.max() - start.min()) / hz
+    assert 0 < span < 1.0, span              # a few microseconds to milliseconds
+
+
+def test_timed_launch_of_empty_batch(gpu):
+    from paper_2305_18236_amd import _native
+    slots = _native.mg_batched_slots(0)
+    stamps = torch.zeros(2 * slots, dtype=torch.int64, device=gpu)
+    arr = (_native.mg_problem * 1)()
+    st, bad, grid = _native.mg_gemm_batched_timed(0, 0, arr, None, 0, torch.cuda.current_stream().cuda_stream,
+                                                  stamps.data_ptr(), 2 * slots)
+    assert (st, grid) == (0, 0)
+    assert int(stamps.abs().sum()) == 0
