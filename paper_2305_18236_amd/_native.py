@@ -39,6 +39,15 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_18236_amd.build` "
                           "(the HIP library is required; there is no CPU fallback)")
+    # torch ships its own HIP runtime under the same soname as the system's
+    # (libamdhip64.so.7).  Whichever is loaded first serves the whole
+    # process, so torch is imported first: the library then shares torch's
+    # runtime, devices and streams instead of bringing in a second one that
+    # torch would later fail to initialise against.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     i64, f32, vp, ch, ci = ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_char, ctypes.c_int
     L.mg_sgemm.argtypes = [ch, ch, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]

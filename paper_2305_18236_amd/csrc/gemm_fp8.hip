@@ -32,6 +32,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "tile_bytes.h"
+#include "epilogue.h"
 
 namespace mg {
 
@@ -307,24 +308,8 @@ void gemm_fp8_kernel(Fp8Args g)
     }
 
     const float alpha = g.alpha, beta = g.beta;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (m >= g.M) continue;
-            float* crow = g.C + m * g.ldc;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const int64_t n = n0 + wn0 + 32 * j + c;
-                if (n < g.N) {
-                    float o = alpha * acc[i][j][r];
-                    if (beta != 0.f) o = __builtin_fmaf(alpha, acc[i][j][r], beta * crow[n]);
-                    crow[n] = o;
-                }
-            }
-        }
-    }
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
 }
 
 template <int BM, int BN, int WM, int WN, bool INTERLEAVE>

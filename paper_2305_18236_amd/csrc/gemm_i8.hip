@@ -24,6 +24,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "tile_bytes.h"
+#include "epilogue.h"
 
 namespace mg {
 
@@ -230,24 +231,8 @@ void gemm_i8_kernel(I8Args g)
 
     // C = alpha*acc + beta*C0 modulo 2^32 (unsigned arithmetic wraps).
     const uint32_t alpha = uint32_t(g.alpha), beta = uint32_t(g.beta);
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (m >= g.M) continue;
-            int32_t* crow = g.C + m * g.ldc;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const int64_t n = n0 + wn0 + 32 * j + c;
-                if (n < g.N) {
-                    uint32_t o = alpha * uint32_t(acc[i][j][r]);
-                    if (beta != 0u) o += beta * uint32_t(crow[n]);
-                    crow[n] = int32_t(o);
-                }
-            }
-        }
-    }
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0u, acc,
+                           [&](int32_t a, int32_t c0) { return int32_t(alpha * uint32_t(a) + beta * uint32_t(c0)); });
 }
 
 // C = beta * C modulo 2^32 (beta == 0 writes zeros without reading C): the

@@ -146,9 +146,13 @@ int auto_splits(int64_t t, int64_t K)
 // Automatic configuration.  Measured on MI355X (FP32 and bf16x3 sweeps over
 // 1024^3 .. 8192^3 and skinny shapes): the 256 x 256 tile is the most
 // efficient whenever the tiles, times the split factor, give every compute
-// unit a workgroup; otherwise the next smaller tile with its split.  Very
-// short K (<= 256) favours 64 x 64 tiles, several per compute unit, whose
-// epilogues overlap other workgroups' matrix work.
+// unit a workgroup; otherwise the next smaller tile with its split.  For FP32
+// with very short K (<= 256) the 128 x 64 tile is chosen instead: several
+// per compute unit, so one workgroup's C0 reads and stores overlap another's
+// matrix work (8192 x 8192 x 256, beta 0.5: 359 us against 373 us with
+// 256 x 256 tiles and 398 us with 64 x 64).  The 16-bit paths keep the
+// ladder there (bf16x3 at the same shape: 222 us with 256 x 256 tiles, 303 us
+// with 64 x 64).
 int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
     const int64_t cus = device_cus();
@@ -173,7 +177,7 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     static const int kBf16Ladder[3] = {1, 2, 4};
     const int* ladder = path == MG_PATH_FP32 ? kFp32Ladder : kBf16Ladder;
     const ConfigTable t = table_of(path);
-    if (K <= 256 && tiles(M, N, 64, 64) >= cus) return ladder[2];
+    if (path == MG_PATH_FP32 && K <= 256 && tiles(M, N, 128, 64) >= cus) return 4;
     for (int i = 0; i < 3; ++i) {
         const mg::SgemmConfig& c = t.cfgs[ladder[i]];
         const int64_t n = tiles(M, N, c.bm, c.bn);

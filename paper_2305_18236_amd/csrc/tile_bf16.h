@@ -30,6 +30,7 @@
 // op(A) row l%32 and the same eight k values of op(B) column l%32 (k block
 // l/32); result register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32].
 #include "common.h"
+#include "epilogue.h"
 
 namespace mg {
 
@@ -483,24 +484,8 @@ MG_DEVICE void bf16_tile(const GemmArgs& g, int tm, int tn, uint16_t* smem)
 
     // Epilogue: C = alpha*acc + beta*C0 (C0 not read when beta == 0).
     const float alpha = g.alpha, beta = g.beta;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t m = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (m >= g.M) continue;
-            float* crow = g.C + m * g.ldc;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const int64_t n = n0 + wn0 + 32 * j + c;
-                if (n < g.N) {
-                    float o = alpha * acc[i][j][r];
-                    if (beta != 0.f) o = __builtin_fmaf(alpha, acc[i][j][r], beta * crow[n]);
-                    crow[n] = o;
-                }
-            }
-        }
-    }
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
 }
 
 }  // namespace mg

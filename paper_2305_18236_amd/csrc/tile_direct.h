@@ -24,6 +24,7 @@
 // of op(A) and of its column of op(B), which is one 16-byte load whenever that
 // operand is stored k-contiguous (A as M x K, B as N x K).
 #include "common.h"
+#include "epilogue.h"
 
 namespace mg {
 
@@ -113,26 +114,10 @@ MG_DEVICE void direct_tile(const GemmArgs& g, int tm, int tn)
         }
     }
 
-    // Epilogue C = alpha*acc + beta*C0 (C0 not read when beta == 0).  Register
-    // r of lane (c, h) holds row 8*(r/4) + 4*h + r%4, column c of its block:
-    // 32 lanes store 32 consecutive floats of one row.
+    // Epilogue C = alpha*acc + beta*C0 (C0 not read when beta == 0).
     const float alpha = g.alpha, beta = g.beta;
-#pragma unroll
-    for (int i = 0; i < V; ++i)
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            const int64_t n = nw + 32 * j + c;
-            if (n >= g.N) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t m = mw + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (m >= g.M) continue;
-                float* cp = g.C + m * g.ldc + n;
-                float o = alpha * acc[i][j][r];
-                if (beta != 0.f) o = __builtin_fmaf(alpha, acc[i][j][r], beta * *cp);
-                *cp = o;
-            }
-        }
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, mw, nw, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
 }
 
 }  // namespace mg

@@ -276,41 +276,77 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
         __syncthreads();
     }
 
-    // Epilogue: C = alpha*acc + beta*C0, once per element.
+    // Epilogue: C = alpha*acc + beta*C0, once per element.  C0 is read
+    // through the pointer C is written through, so loads placed between the
+    // stores could not be moved ahead of them and each would wait a whole
+    // memory round trip; the C0 values of one accumulator block row (half of
+    // it for the largest grids) are therefore all loaded first, then stored.
     const float alpha = g.alpha, beta = g.beta;
     const int64_t ncol = n0 + wn0 + H * c;   // first of this lane's H columns
+    auto row_of = [&](int i, int r) { return m0 + wm0 + V * (8 * (r >> 2) + 4 * h + (r & 3)) + i; };
+    // columns ncol .. ncol+H-1 all inside the stored triangle
+    auto whole = [&](int64_t m) { return UPLO == 0 || (UPLO == 1 ? ncol + H - 1 <= m : ncol >= m); };
+    // one 16-byte (H = 4) or 8-byte (H = 2) access per row: vec_c makes
+    // C and ldc 16-byte aligned and ncol is a multiple of H
+    auto vec_row = [&](int64_t m) { return (H == 4 || H == 2) && g.vec_c && ncol + H - 1 < g.N && whole(m); };
+    auto inside = [&](int64_t m, int j) {
+        return ncol + j < g.N && (UPLO == 0 || (UPLO == 1 ? ncol + j <= m : ncol + j >= m));
+    };
+    // rows per batch: half a block row for the largest accumulator grids,
+    // whose registers leave no room for 16 x H loaded values and addresses
+    constexpr int RB = V * H >= 16 ? 4 : 16;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row_in_block = 8 * (r >> 2) + 4 * h + (r & 3);
-            const int64_t m = m0 + wm0 + V * row_in_block + i;
-            if (m >= g.M) continue;
-            float* cp = g.C + m * g.ldc + ncol;
-            float out[H];
+        for (int r0 = 0; r0 < 16; r0 += RB) {
+            float c0[RB][H];
+            if (beta != 0.f) {
+                // Out-of-range rows and columns read a clamped in-range
+                // element that is never stored (nor is anything outside the
+                // triangle), so the loads need no branches.
+                const bool vec = (H == 4 || H == 2) && g.vec_c && ncol + H - 1 < g.N;
 #pragma unroll
-            for (int j = 0; j < H; ++j) out[j] = acc[i][j][r];
-            // columns ncol .. ncol+H-1 all inside the stored triangle
-            const bool whole = UPLO == 0 || (UPLO == 1 ? ncol + H - 1 <= m : ncol >= m);
-            if (H == 4 && g.vec_c && ncol + 3 < g.N && whole) {
-                floatx4 o = {alpha * out[0], alpha * out[1], alpha * out[2], alpha * out[3]};
-                if (beta != 0.f) {
-                    const floatx4 c0 = *reinterpret_cast<const floatx4*>(cp);
-                    o[0] = __builtin_fmaf(alpha, out[0], beta * c0[0]);
-                    o[1] = __builtin_fmaf(alpha, out[1], beta * c0[1]);
-                    o[2] = __builtin_fmaf(alpha, out[2], beta * c0[2]);
-                    o[3] = __builtin_fmaf(alpha, out[3], beta * c0[3]);
-                }
-                *reinterpret_cast<floatx4*>(cp) = o;
-            } else {
+                for (int rr = 0; rr < RB; ++rr) {
+                    const int64_t m = row_of(i, r0 + rr);
+                    const float* cp = g.C + (m < g.M ? m : g.M - 1) * g.ldc;
+                    if (vec) {
+                        if constexpr (H == 4) {
+                            const floatx4 v = *reinterpret_cast<const floatx4*>(cp + ncol);
 #pragma unroll
-                for (int j = 0; j < H; ++j) {
-                    const bool tri = UPLO == 0 || (UPLO == 1 ? ncol + j <= m : ncol + j >= m);
-                    if (ncol + j < g.N && tri) {
-                        float o = alpha * out[j];
-                        if (beta != 0.f) o = __builtin_fmaf(alpha, out[j], beta * cp[j]);
-                        cp[j] = o;
+                            for (int j = 0; j < H; ++j) c0[rr][j] = v[j];
+                        } else if constexpr (H == 2) {
+                            const floatx2 v = *reinterpret_cast<const floatx2*>(cp + ncol);
+#pragma unroll
+                            for (int j = 0; j < H; ++j) c0[rr][j] = v[j];
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < H; ++j) c0[rr][j] = cp[ncol + j < g.N ? ncol + j : g.N - 1];
                     }
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const int r = r0 + rr;
+                const int64_t m = row_of(i, r);
+                if (m >= g.M) continue;
+                float* cp = g.C + m * g.ldc + ncol;
+                float o[H];
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    o[j] = beta != 0.f ? __builtin_fmaf(alpha, acc[i][j][r], beta * c0[rr][j]) : alpha * acc[i][j][r];
+                if (vec_row(m)) {
+                    if constexpr (H == 4) {
+                        const floatx4 v = {o[0], o[1], o[2], o[3]};
+                        *reinterpret_cast<floatx4*>(cp) = v;
+                    } else if constexpr (H == 2) {
+                        const floatx2 v = {o[0], o[1]};
+                        *reinterpret_cast<floatx2*>(cp) = v;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+                        if (inside(m, j)) cp[j] = o[j];
                 }
             }
         }

@@ -144,3 +144,20 @@ def test_syr2k_split_plan(native):
         assert native.mg_syr2k_workspace_size(0, 100, 1000) == 4 * 100 * 100 * 4
     finally:
         native.mg_force_splits(0, -1)
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library before anything else imports torch must not bring
+    a second HIP runtime into the process (torch's and the system's share a
+    soname, and the first one loaded serves both)."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r)\n"
+            "from paper_2305_18236_amd import _native\n"
+            "_native.lib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "assert len(libs) == 1, libs\n"
+            "assert next(iter(libs)).startswith(os.path.dirname(torch.__file__)), libs\n") % ROOT
+    subprocess.run([sys.executable, "-c", code], check=True, timeout=300)
