@@ -27,17 +27,25 @@ MG_DEVICE void store_acc_blocks(T* C, int64_t ldc, int64_t M, int64_t N, int64_t
 #pragma unroll
         for (int r0 = 0; r0 < 16; r0 += RB) {
             T c0[RB][H];
+            if (read_c0) {
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) {
-                const int r = r0 + rr;
-                const int64_t m = mw + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                for (int rr = 0; rr < RB; ++rr) {
+                    // out-of-range lanes read a clamped in-range element
+                    // that is never stored, so the loads need no branches
+                    const int r = r0 + rr;
+                    const int64_t m = mw + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const T* crow = C + (m < M ? m : M - 1) * ldc;
 #pragma unroll
-                for (int j = 0; j < H; ++j) {
-                    // out-of-range lanes read a clamped in-range element that
-                    // is never stored, so the loads need no branches
-                    const int64_t n = nw + 32 * j + c;
-                    c0[rr][j] = read_c0 ? C[(m < M ? m : M - 1) * ldc + (n < N ? n : N - 1)] : T(0);
+                    for (int j = 0; j < H; ++j) {
+                        const int64_t n = nw + 32 * j + c;
+                        c0[rr][j] = crow[n < N ? n : N - 1];
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+                    for (int j = 0; j < H; ++j) c0[rr][j] = T(0);
             }
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {

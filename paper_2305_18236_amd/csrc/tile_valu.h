@@ -86,34 +86,50 @@ MG_DEVICE void valu_tile(const GemmArgs& g, int tm, int tn, float* smem)
         __syncthreads();
     }
 
-    // Epilogue: C = alpha*acc + beta*C0 (C0 not read when beta == 0).
+    // Epilogue: C = alpha*acc + beta*C0 (C0 not read when beta == 0).  C0 is
+    // read through the pointer C is written through, so a load placed between
+    // the stores could not be moved ahead of them: all 16 of the thread's C0
+    // pieces are loaded first (out-of-range rows and columns read a clamped
+    // in-range element that is never stored), then the results are stored.
     const float alpha = g.alpha, beta = g.beta;
+    auto row_of = [&](int i) { return m0 + (i < 4 ? ty * 4 + i : 64 + ty * 4 + (i - 4)); };
+    floatx4 c0[8][2];
+    if (beta != 0.f) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t m = row_of(i);
+            const float* crow = g.C + (m < g.M ? m : g.M - 1) * g.ldc;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int64_t n = n0 + half * 64 + tx * 4;
+                if (g.vec_c && n + 3 < g.N) {
+                    c0[i][half] = *reinterpret_cast<const floatx4*>(crow + n);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) c0[i][half][e] = crow[n + e < g.N ? n + e : g.N - 1];
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int64_t m = m0 + (i < 4 ? ty * 4 + i : 64 + ty * 4 + (i - 4));
+        const int64_t m = row_of(i);
         if (m >= g.M) continue;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int64_t n = n0 + half * 64 + tx * 4;
             float* cp = g.C + m * g.ldc + n;
             const float* v = &acc[i][half * 4];
-            if (g.vec_c && n + 3 < g.N) {
-                floatx4 o = {alpha * v[0], alpha * v[1], alpha * v[2], alpha * v[3]};
-                if (beta != 0.f) {
-                    const floatx4 c0 = *reinterpret_cast<const floatx4*>(cp);
+            floatx4 o;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) o[e] = __builtin_fmaf(alpha, v[e], beta * c0[e]);
-                }
+            for (int e = 0; e < 4; ++e)
+                o[e] = beta != 0.f ? __builtin_fmaf(alpha, v[e], beta * c0[i][half][e]) : alpha * v[e];
+            if (g.vec_c && n + 3 < g.N) {
                 *reinterpret_cast<floatx4*>(cp) = o;
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (n + e < g.N) {
-                        float o = alpha * v[e];
-                        if (beta != 0.f) o = __builtin_fmaf(alpha, v[e], beta * cp[e]);
-                        cp[e] = o;
-                    }
-                }
+                for (int e = 0; e < 4; ++e)
+                    if (n + e < g.N) cp[e] = o[e];
             }
         }
     }
