@@ -34,6 +34,8 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
 M = N = K = 8192
 ALPHA, BETA = 1.5, 0.5
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sgemm_f32_8192_nn_traffic.md")
+PROFILE_SMALLK = os.path.join(ROOT, "profiles", "sgemm_small_k_traffic.md")
+SMALLK_SHAPE = (8192, 8192, 256)
 KERNEL_SOURCES = ["paper_2305_18236_amd/csrc/gemm_f32.hip", "paper_2305_18236_amd/csrc/tile_f32.h",
                   "paper_2305_18236_amd/csrc/common.h"]
 
@@ -46,13 +48,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+def measured_traffic(profile=PROFILE_TRAFFIC):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+    if not os.path.exists(profile):
         return None
     vals = {}
-    for line in open(PROFILE_TRAFFIC):
+    for line in open(profile):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
@@ -135,7 +137,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling", "engine", "types", "syr2k"],
+    ap.add_argument("--workload", choices=["sgemm", "batched", "chain", "fp8", "sweep", "tiling", "engine", "types", "syr2k",
+                             "smallk"],
                     default="sgemm",
                     help="sgemm: the FP32 8192^3 line (default); batched: 512 uneven problems; "
                          "chain: forward + backward of Y = (X W1) W2; fp8: FP8 path at 8192^3; "
@@ -181,6 +184,8 @@ def main():
         return bench_types(args, torch, si, native, dev)
     if args.workload == "syr2k":
         return bench_syr2k(args, torch, si, native, dev)
+    if args.workload == "smallk":
+        return bench_smallk(args, torch, si, native, dev)
 
     A_h = si.uniform((M, K), si.seed_for(2, "A")).reshape(-1)
     B_h = si.uniform((K, N), si.seed_for(2, "B")).reshape(-1)
@@ -708,6 +713,51 @@ def bench_types(args, torch, si, native, dev):
            "roofline": {"bound": "mfma", "achieved": rows["int8_gemm_only"]["tops"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOP/s", "frac": rows["int8_gemm_only"]["frac_of_int8_peak"], "traffic": None,
                         "kernel": "gemm_i8_kernel<256,256,128,64,interleaved>"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_smallk(args, torch, si, native, dev):
+    """The small-K shape of the FP32 sweep, 8192 x 8192 x 256 NN (alpha 1.5,
+    beta 0.5, U[-1, 1]), on the FP32 and bf16x3 paths.  Algorithmic HBM bytes
+    per launch: 4(MK + KN) + 8MN (A and B read once, C0 read, C written);
+    at 62 flop per byte the shape is still matrix-core bound on paper (ridge
+    19.7 flop/B for FP32), but its K loop is 8 panels deep (BK = 32), so the
+    epilogue's C traffic weighs 32 times more than at K = 8192."""
+    m, n, k = SMALLK_SHAPE
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    A = torch.from_numpy(si.uniform((m * k,), si.seed_for(2, "A"))).to(dev)
+    B = torch.from_numpy(si.uniform((k * n,), si.seed_for(2, "B"))).to(dev)
+    C0 = torch.from_numpy(si.uniform((m * n,), si.seed_for(2, "C"))).to(dev)
+    flops = 2.0 * m * n * k
+    nbytes = 4.0 * (m * k + k * n) + 8.0 * m * n
+    rows = {}
+    for name, pid in (("fp32", 0), ("bf16x3", 1)):
+        C = C0.clone()
+        need = native.mg_gemm_workspace_size(pid, "N", "N", m, n, k)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+        def run():
+            native.check(native.mg_gemm(pid, "N", "N", m, n, k, ALPHA, A.data_ptr(), k, B.data_ptr(), n, BETA,
+                                        C.data_ptr(), n, ws.data_ptr(), need, sp), "mg_gemm")
+
+        ms = _time_ms(run, args.steps, args.warmup, torch, stream)
+        rows[name] = {"ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 2),
+                      "algorithmic_gbps": round(nbytes / ms / 1e6, 1), "config": native.mg_tuned_config(pid, m, n, k)}
+        del C, ws
+    f = rows["fp32"]
+    traffic = measured_traffic(PROFILE_SMALLK)
+    out = {"metric": "FP32 SGEMM TFLOP/s and HBM GB/s at 8192x8192x256", "unit": "TFLOP/s", "value": f["tflops"],
+           "ms_per_step": f["ms"], "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sgemm_small_k_8192x8192x256_nn", "M": m, "N": n, "K": k, "layout": "NN",
+                      "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]"},
+           "roofline": {"bound": "mfma", "achieved": f["tflops"], "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                        "frac": round(f["tflops"] / PEAK_TFLOPS["fp32"], 4), "traffic": traffic,
+                        "kernel": "sgemm_mfma_kernel<128,64,32,64,32,NN>",
+                        "algorithmic_bytes_per_launch": nbytes,
+                        "hbm_gbps_measured": None if traffic is None else round(traffic / f["ms"] / 1e6, 1)},
            "rows": rows}
     print(json.dumps(out), flush=True)
 
