@@ -90,52 +90,76 @@ hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hi
 // threads per 128 x 128 tile; the tile goes through LDS so that both stored
 // layouts write whole 16-byte row chunks.
 constexpr int PT = 128;          // pack tile
-constexpr int PROW = PT + 8;     // LDS row of the pack tile (bf16)
+constexpr int PROW = PT + 8;     // LDS row of the pack tile (bf16), T == false
+
+// T == true: unpadded 128-element rows whose sixteen 16-byte chunks are
+// permuted by an XOR with (r >> 2) % 16, so that the 8-byte writes of a
+// half-wave (32 rows four apart) meet at most two to a bank and the 16-byte
+// reads of the write-out not at all (padded and unswizzled, the writes meet
+// eight to a bank).  Returns the element offset of element k of row r.
+MG_DEVICE int pt_swizzle(int r, int k) { return 8 * (((k >> 3) ^ (r >> 2)) & 15) + (k & 7); }
 
 template <bool T, int TERMS>
 __global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict__ X, int64_t ldx, int64_t R,
                                                         int64_t Kd, int vec, uint16_t* __restrict__ hi,
                                                         uint16_t* __restrict__ lo, int64_t ldq)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t th[PT * PROW];
-    __shared__ __attribute__((aligned(16))) uint16_t tl[TERMS == 3 ? PT * PROW : 8];
+    constexpr int ROW = T ? PT : PROW;
+    __shared__ __attribute__((aligned(16))) uint16_t th[PT * ROW];
+    __shared__ __attribute__((aligned(16))) uint16_t tl[TERMS == 3 ? PT * ROW : 8];
     const int tid = threadIdx.x;
-    const int64_t k0 = int64_t(blockIdx.x) * PT, r0 = int64_t(blockIdx.y) * PT;
+    // blockIdx.x runs along the stored rows (over k tiles when T is false,
+    // over row tiles of op(X) when T is true), so that consecutive workgroups
+    // read neighbouring pieces of the same stored rows (measured: the other
+    // order makes either pack about 20 % slower)
+    const int64_t k0 = int64_t(T ? blockIdx.y : blockIdx.x) * PT, r0 = int64_t(T ? blockIdx.x : blockIdx.y) * PT;
     const int64_t sr0 = T ? k0 : r0, sc0 = T ? r0 : k0;      // stored tile origin
     const int64_t SRn = T ? Kd : R, SCn = T ? R : Kd;         // stored valid extent
+    // 16 chunks of 4 floats per thread.  T == false: chunk s is stored row
+    // id / 32, stored columns 4*(id % 32) .. +3, id = tid + 256*s.  T == true:
+    // chunks 4b .. 4b+3 are the 4 x 4 block of stored rows 4*(id / 32) .. +3
+    // (four k) and stored columns 4*(id % 32) .. +3 (four logical rows),
+    // id = tid + 256*b, so each logical row's four k become one 8-byte write.
+    auto stored_row = [&](int s) { return T ? 4 * ((tid + 256 * (s >> 2)) / 32) + (s & 3) : (tid + 256 * s) / 32; };
+    auto stored_col = [&](int s) { return T ? 4 * ((tid + 256 * (s >> 2)) % 32) : 4 * ((tid + 256 * s) % 32); };
     floatx4 v[16];
     if (vec && sr0 + PT <= SRn && sc0 + PT <= SCn) {          // wave-uniform: interior tile
         const float* __restrict__ base = X + sr0 * ldx + sc0;
         const uint32_t ld32 = uint32_t(ldx);
 #pragma unroll
+        for (int s = 0; s < 16; ++s) v[s] = load16(base, (uint32_t(stored_row(s)) * ld32 + uint32_t(stored_col(s))) * 4u);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) v[s] = fetch4_guarded(X, ldx, sr0 + stored_row(s), sc0 + stored_col(s), SRn, SCn, vec);
+    }
+    auto convert = [&](floatx4 x, uint32_t (&h)[2], uint32_t (&l)[2]) {
+        if constexpr (TERMS == 3) split4(x, h, l);
+        else convert4<TERMS>(x, h);
+    };
+    if (!T) {
+#pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const uint32_t id = tid + 256 * s;
-            v[s] = load16(base, ((id / 32) * ld32 + 4 * (id % 32)) * 4u);
+            // stored row = logical row, columns = k .. k+3
+            uint32_t h[2], l[2];
+            convert(v[s], h, l);
+            const int off = stored_row(s) * PROW + stored_col(s);
+            *reinterpret_cast<uint2*>(&th[off]) = make_uint2(h[0], h[1]);
+            if (TERMS == 3) *reinterpret_cast<uint2*>(&tl[off]) = make_uint2(l[0], l[1]);
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int id = tid + 256 * s;
-            v[s] = fetch4_guarded(X, ldx, sr0 + id / 32, sc0 + 4 * (id % 32), SRn, SCn, vec);
-        }
-    }
+        for (int b = 0; b < 4; ++b) {
+            const int id = tid + 256 * b;
+            const int kk = 4 * (id / 32);            // first k of the block
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int id = tid + 256 * s;
-        const int sr = id / 32, scol = 4 * (id % 32);
-        uint32_t h[2], l[2];
-        if constexpr (TERMS == 3) split4(v[s], h, l);
-        else convert4<TERMS>(v[s], h);
-        if (!T) {
-            // stored row = logical row, columns = k .. k+3
-            *reinterpret_cast<uint2*>(&th[sr * PROW + scol]) = make_uint2(h[0], h[1]);
-            if (TERMS == 3) *reinterpret_cast<uint2*>(&tl[sr * PROW + scol]) = make_uint2(l[0], l[1]);
-        } else {
-            // stored row = k, columns = four consecutive logical rows
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                th[(scol + b) * PROW + sr] = uint16_t(h[b >> 1] >> (16 * (b & 1)));
-                if (TERMS == 3) tl[(scol + b) * PROW + sr] = uint16_t(l[b >> 1] >> (16 * (b & 1)));
+            for (int c = 0; c < 4; ++c) {
+                const int r = 4 * (id % 32) + c;     // logical row
+                const floatx4 x = {v[4 * b][c], v[4 * b + 1][c], v[4 * b + 2][c], v[4 * b + 3][c]};
+                uint32_t h[2], l[2];
+                convert(x, h, l);
+                const int off = r * PT + pt_swizzle(r, kk);
+                *reinterpret_cast<uint2*>(&th[off]) = make_uint2(h[0], h[1]);
+                if (TERMS == 3) *reinterpret_cast<uint2*>(&tl[off]) = make_uint2(l[0], l[1]);
             }
         }
     }
@@ -144,9 +168,10 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict_
     for (int s = 0; s < 8; ++s) {
         const int id = tid + 256 * s;
         const int r = id / 16, c = 8 * (id % 16);
-        *reinterpret_cast<uint4*>(hi + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&th[r * PROW + c]);
+        const int off = T ? r * PT + pt_swizzle(r, c) : r * PROW + c;
+        *reinterpret_cast<uint4*>(hi + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&th[off]);
         if (TERMS == 3)
-            *reinterpret_cast<uint4*>(lo + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tl[r * PROW + c]);
+            *reinterpret_cast<uint4*>(lo + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tl[off]);
     }
 }
 
@@ -154,7 +179,7 @@ hipError_t launch_bf16_pack(bool trans, int terms, const float* X, int64_t ldx, 
                             bool vec, uint16_t* hi, uint16_t* lo, int64_t ldq, int64_t Rp, int64_t Kp,
                             hipStream_t stream)
 {
-    const dim3 grid(unsigned(Kp / PT), unsigned(Rp / PT)), block(256);
+    const dim3 grid(unsigned(trans ? Rp / PT : Kp / PT), unsigned(trans ? Kp / PT : Rp / PT)), block(256);
     switch (terms) {
     case 3:
         if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 3>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), hi, lo, ldq);

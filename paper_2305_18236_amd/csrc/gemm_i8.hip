@@ -32,7 +32,14 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 typedef int intx16 __attribute__((ext_vector_type(16)));
 
 constexpr int IT = 128;          // pack tile (rows x bytes)
-constexpr int IROW = IT + 16;    // LDS row of the pack tile (bytes)
+constexpr int IROW = IT + 16;    // LDS row of the pack tile (bytes), T == false
+
+// T == true: unpadded 128-byte rows whose eight 16-byte chunks are permuted
+// by an XOR with (r >> 4) % 8, so that the 4-byte writes of a wave (eight
+// rows sixteen apart, eight k words) meet at most two to a bank and the
+// 16-byte reads of the write-out not at all (padded and unswizzled, the
+// writes meet eight to a bank).  Returns the byte offset of byte k of row r.
+MG_DEVICE int it_swizzle(int r, int k) { return 16 * (((k >> 4) ^ (r >> 4)) & 7) + (k & 15); }
 
 // One workgroup of 256 threads per 128 x 128 tile of the logical R x Kd
 // matrix op(X).  T == false: X stored R x Kd (k contiguous); T == true:
@@ -41,28 +48,35 @@ template <bool T>
 __global__ __launch_bounds__(256) void i8_pack_kernel(const int8_t* __restrict__ X, int64_t ldx, int64_t R,
                                                       int64_t Kd, int vec, int8_t* __restrict__ q, int64_t ldq)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t tile[IT * IROW];
+    constexpr int ROW = T ? IT : IROW;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[IT * ROW];
     const int tid = threadIdx.x;
-    const int64_t k0 = int64_t(blockIdx.x) * IT, r0 = int64_t(blockIdx.y) * IT;
+    // blockIdx.x runs along the stored rows (over k tiles when T is false,
+    // over row tiles of op(X) when T is true), so that consecutive workgroups
+    // read neighbouring pieces of the same stored rows (measured: the other
+    // order makes either pack about 20 % slower)
+    const int64_t k0 = int64_t(T ? blockIdx.y : blockIdx.x) * IT, r0 = int64_t(T ? blockIdx.x : blockIdx.y) * IT;
     const int64_t sr0 = T ? k0 : r0, sc0 = T ? r0 : k0;      // stored tile origin
     const int64_t SRn = T ? Kd : R, SCn = T ? R : Kd;         // stored valid extent
 
-    // 4 chunks of 16 stored bytes per thread: chunk id covers stored row
-    // id / 8 and stored columns 16*(id % 8) .. +15.
+    // 4 chunks of 16 stored bytes per thread.  T == false: chunk s is stored
+    // row id / 8, stored columns 16*(id % 8) .. +15, id = tid + 256*s.
+    // T == true: the 4 x 16 block of stored rows 4*(tid / 8) .. +3 (four k)
+    // and stored columns 16*(tid % 8) .. +15 (sixteen logical rows), chunk s
+    // being stored row 4*(tid / 8) + s, so each logical row's four k become
+    // one 4-byte word.  Either way 8 lanes read one 128-byte stored row.
+    auto stored_row = [&](int s) { return T ? 4 * (tid / 8) + s : (tid + 256 * s) / 8; };
+    auto stored_col = [&](int s) { return T ? 16 * (tid % 8) : 16 * ((tid + 256 * s) % 8); };
     uint4 v[4];
     if (vec && sr0 + IT <= SRn && sc0 + IT <= SCn) {          // wave-uniform: interior tile
         const int8_t* __restrict__ base = X + sr0 * ldx + sc0;
         const uint32_t ld32 = uint32_t(ldx);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint32_t id = tid + 256 * s;
-            v[s] = load16u(base, (id / 8) * ld32 + 16 * (id % 8));
-        }
+        for (int s = 0; s < 4; ++s) v[s] = load16u(base, uint32_t(stored_row(s)) * ld32 + uint32_t(stored_col(s)));
     } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int id = tid + 256 * s;
-            const int64_t gr = sr0 + id / 8, gc = sc0 + 16 * (id % 8);
+            const int64_t gr = sr0 + stored_row(s), gc = sc0 + stored_col(s);
             uint8_t b[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e)
@@ -75,18 +89,21 @@ __global__ __launch_bounds__(256) void i8_pack_kernel(const int8_t* __restrict__
             v[s] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
+    if (!T) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int id = tid + 256 * s;
-        const int sr = id / 8, scol = 16 * (id % 8);
-        if (!T) {
-            // stored row = logical row, columns = k .. k+15
-            *reinterpret_cast<uint4*>(&tile[sr * IROW + scol]) = v[s];
-        } else {
-            // stored row = k, columns = 16 consecutive logical rows
-            const uint32_t w[4] = {v[s].x, v[s].y, v[s].z, v[s].w};
+        for (int s = 0; s < 4; ++s)   // stored row = logical row, columns = k .. k+15
+            *reinterpret_cast<uint4*>(&tile[stored_row(s) * IROW + stored_col(s)]) = v[s];
+    } else {
+        const int kk = 4 * (tid / 8);                  // first k of the block
+        const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w}, {v[1].x, v[1].y, v[1].z, v[1].w},
+                                  {v[2].x, v[2].y, v[2].z, v[2].w}, {v[3].x, v[3].y, v[3].z, v[3].w}};
 #pragma unroll
-            for (int e = 0; e < 16; ++e) tile[(scol + e) * IROW + sr] = uint8_t(w[e >> 2] >> (8 * (e & 3)));
+        for (int c = 0; c < 16; ++c) {
+            const int r = 16 * (tid % 8) + c;          // logical row
+            const int sh = 8 * (c & 3);
+            const uint32_t word = ((w[0][c >> 2] >> sh) & 0xffu) | (((w[1][c >> 2] >> sh) & 0xffu) << 8) |
+                                  (((w[2][c >> 2] >> sh) & 0xffu) << 16) | (((w[3][c >> 2] >> sh) & 0xffu) << 24);
+            *reinterpret_cast<uint32_t*>(&tile[r * IT + it_swizzle(r, kk)]) = word;
         }
     }
     __syncthreads();
@@ -94,14 +111,15 @@ __global__ __launch_bounds__(256) void i8_pack_kernel(const int8_t* __restrict__
     for (int s = 0; s < 4; ++s) {
         const int id = tid + 256 * s;
         const int r = id / 8, c = 16 * (id % 8);
-        *reinterpret_cast<uint4*>(q + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tile[r * IROW + c]);
+        const int off = T ? r * IT + it_swizzle(r, c) : r * IROW + c;
+        *reinterpret_cast<uint4*>(q + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tile[off]);
     }
 }
 
 hipError_t launch_i8_pack(bool trans, const int8_t* X, int64_t ldx, int64_t R, int64_t Kd, bool vec, int8_t* q,
                           int64_t ldq, int64_t Rp, int64_t Kp, hipStream_t stream)
 {
-    const dim3 grid(unsigned(Kp / IT), unsigned(Rp / IT)), block(256);
+    const dim3 grid(unsigned(trans ? Rp / IT : Kp / IT), unsigned(trans ? Kp / IT : Rp / IT)), block(256);
     if (trans) hipLaunchKernelGGL(i8_pack_kernel<true>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq);
     else hipLaunchKernelGGL(i8_pack_kernel<false>, grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, ldq);
     return hipGetLastError();
