@@ -181,7 +181,18 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     for (int i = 0; i < 3; ++i) {
         const mg::SgemmConfig& c = t.cfgs[ladder[i]];
         const int64_t n = tiles(M, N, c.bm, c.bn);
-        if (n * auto_splits(n, K) >= cus) return ladder[i];
+        const int s = auto_splits(n, K);
+        if (n * s < cus) continue;
+        // FP32: when this tile needs K ranges as short as kMinRange to fill
+        // the GPU and the next smaller tile fills it unsplit, the smaller one
+        // wins (1024^3, beta 0.5: 64 x 64 unsplit 31.6 us, 128 x 128 in four
+        // 256-deep ranges plus the reduction 37.6 us).  bf16x3 keeps the split
+        // there (25.0 us against 32.0 us).
+        if (path == MG_PATH_FP32 && s > 1 && K / s <= kMinRange && i + 1 < 3) {
+            const mg::SgemmConfig& d = t.cfgs[ladder[i + 1]];
+            if (tiles(M, N, d.bm, d.bn) >= cus) return ladder[i + 1];
+        }
+        return ladder[i];
     }
     return ladder[2];
 }
