@@ -911,7 +911,6 @@ int run_batched(int path, int64_t count, const mg_problem* problems, void* works
     const ConfigTable t = table_of(path);
     const int* cfgs = batched_cfgs(path);
     std::vector<mg::BatchProblem> host;
-    std::vector<int64_t> cost;
     host.reserve(size_t(count));
     for (int64_t i = 0; i < count; ++i) {
         const mg_problem& q = problems[i];
