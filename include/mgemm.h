@@ -38,6 +38,11 @@
  *   device call.  Other codes are the MG_ERR_* values below; a HIP runtime
  *   error e is returned as MG_ERR_HIP - e.  mg_status_string() describes any
  *   code.
+ * Sizes.  Every compute entry point rejects a dimension above INT_MAX with
+ *   MG_ERR_TOO_LARGE.  For such a dimension the query functions answer
+ *   without computing: the *_workspace_size functions return 0,
+ *   mg_split_count 1, and mg_tuned_config, mg_batched_config,
+ *   mg_fp8_packed_size and mg_i8_packed_size MG_ERR_TOO_LARGE.
  */
 #ifndef MGEMM_H
 #define MGEMM_H

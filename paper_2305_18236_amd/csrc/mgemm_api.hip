@@ -70,6 +70,10 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 // 16-byte panel loads with 32-bit in-panel offsets (see GemmArgs::vec_a).
 bool fast_operand(const void* p, int64_t ld) { return aligned16(p) && ld % 4 == 0 && ld < (int64_t(1) << 22) - 64; }
 
+// A dimension no compute entry point accepts (they return MG_ERR_TOO_LARGE);
+// the query functions answer for it without forming products that overflow.
+bool beyond_int(int64_t a, int64_t b, int64_t c) { return a > INT_MAX || b > INT_MAX || c > INT_MAX; }
+
 int64_t tiles(int64_t M, int64_t N, int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); }
 
 struct ConfigTable {
@@ -112,8 +116,10 @@ bool config_valid(int path, int cfg)
 int bucket(int64_t x)
 {
     if (x <= 1) return 0;
-    int b = 63 - __builtin_clzll(uint64_t(x));
-    if (2 * x >= (int64_t(3) << b)) ++b;   // round to the nearer power of two
+    int b = 63 - __builtin_clzll(uint64_t(x));   // 2^b <= x < 2^(b+1), b >= 1
+    // round to the nearer power of two: x >= 1.5 * 2^b, written without
+    // forming 2x (which overflows for x near INT64_MAX)
+    if (x - (int64_t(1) << b) >= (int64_t(1) << (b - 1))) ++b;
     return b < kBuckets ? b : kBuckets - 1;
 }
 
@@ -138,7 +144,7 @@ constexpr int kMaxSplits = 16;
 int auto_splits(int64_t t, int64_t K)
 {
     const int64_t cus = device_cus();
-    if (t >= cus) return 1;
+    if (t <= 0 || t >= cus) return 1;   // no tiles (M or N is 0): nothing to split
     const int64_t s = std::min<int64_t>({(cus + t - 1) / t, K / kMinRange, kMaxSplits});
     return s < 2 ? 1 : int(s);
 }
@@ -582,7 +588,7 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int64_t N, int64_t K)
 {
     (void)transA; (void)transB;
-    if (M <= 0 || N <= 0 || K <= 0 || !float_path(path)) return 0;
+    if (M <= 0 || N <= 0 || K <= 0 || !float_path(path) || beyond_int(M, N, K)) return 0;
     if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
     size_t total = 0;
     if (is_16bit(path) && bf16_prepack_pays(path, M, N, K))
@@ -595,6 +601,7 @@ int mg_fp8_packed_size(int64_t R, int64_t K, size_t* q_bytes, size_t* scale_byte
 {
     if (R < 0) return -1;
     if (K < 0) return -2;
+    if (beyond_int(R, K, 0)) return MG_ERR_TOO_LARGE;
     if (q_bytes) *q_bytes = fp8_q_bytes(R, K);
     if (scale_bytes) *scale_bytes = fp8_s_bytes(R, K);
     return MG_OK;
@@ -688,13 +695,13 @@ int mg_syr2k(int path, char uplo, char trans, int64_t N, int64_t K, float alpha,
 
 size_t mg_syr2k_workspace_size(int path, int64_t N, int64_t K)
 {
-    if (path != MG_PATH_FP32 || N <= 0 || K <= 0) return 0;
+    if (path != MG_PATH_FP32 || N <= 0 || K <= 0 || beyond_int(N, K, 0)) return 0;
     return syr2k_plan(N, K).bytes;
 }
 
 size_t mg_gemm_i8_workspace_size(int64_t M, int64_t N, int64_t K)
 {
-    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (M <= 0 || N <= 0 || K <= 0 || beyond_int(M, N, K)) return 0;
     return i8_workspace(M, N, K).total;
 }
 
@@ -729,6 +736,7 @@ int mg_i8_packed_size(int64_t R, int64_t K, size_t* bytes)
 {
     if (R < 0) return -1;
     if (K < 0) return -2;
+    if (beyond_int(R, K, 0)) return MG_ERR_TOO_LARGE;
     if (bytes) *bytes = fp8_q_bytes(R, K);
     return MG_OK;
 }
@@ -815,7 +823,7 @@ int mg_force_splits(int path, int splits)
 
 int mg_split_count(int path, int64_t M, int64_t N, int64_t K)
 {
-    if (table_of(path).n == 0 || M <= 0 || N <= 0 || K <= 0) return 1;
+    if (table_of(path).n == 0 || M <= 0 || N <= 0 || K <= 0 || beyond_int(M, N, K)) return 1;
     return split_plan(path, pick_config(path, M, N, K), M, N, K).splits;
 }
 
@@ -866,18 +874,20 @@ int mg_load_tuning(const char* path)
 int mg_tuned_config(int path, int64_t M, int64_t N, int64_t K)
 {
     if (!valid_path(path) || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    if (beyond_int(M, N, K)) return MG_ERR_TOO_LARGE;
     return pick_config(path, M, N, K);
 }
 
 int mg_batched_config(int path, int64_t M, int64_t N, int64_t K)
 {
     if (!batched_path(path) || M < 0 || N < 0 || K < 0) return MG_ERR_UNSUPPORTED;
+    if (beyond_int(M, N, K)) return MG_ERR_TOO_LARGE;
     return batched_cfgs(path)[choose_batched_variant(path, M, N, K)];
 }
 
 size_t mg_gemm_batched_workspace_size(int path, int64_t count)
 {
-    if (!batched_path(path)) return 0;
+    if (!batched_path(path) || count < 0 || count > INT_MAX) return 0;
     return batched_workspace(count);
 }
 

@@ -161,3 +161,22 @@ def test_library_shares_torchs_hip_runtime():
             "assert len(libs) == 1, libs\n"
             "assert next(iter(libs)).startswith(os.path.dirname(torch.__file__)), libs\n") % ROOT
     subprocess.run([sys.executable, "-c", code], check=True, timeout=300)
+
+
+def test_queries_on_empty_and_huge_shapes(native):
+    """Configuration and size queries stay defined at the edges: no tiles
+    (M or N = 0) and dimensions beyond what any compute entry point takes."""
+    for path in (0, 1, 2, 3, 4):
+        assert 0 <= native.mg_tuned_config(path, 0, 5, 5) < native.mg_num_configs(path)
+        assert 0 <= native.mg_tuned_config(path, 5, 0, 5) < native.mg_num_configs(path)
+        assert native.mg_tuned_config(path, 2 ** 31, 5, 5) == -102
+        assert native.mg_split_count(path, 2 ** 62, 2 ** 62, 2 ** 62) == 1
+        assert native.mg_gemm_workspace_size(path, "N", "N", 2 ** 63 - 1, 8, 8) == 0
+    assert native.mg_batched_config(0, 0, 0, 0) >= 0
+    assert native.mg_batched_config(0, 8, 8, 2 ** 40) == -102
+    assert native.mg_gemm_i8_workspace_size(2 ** 40, 8, 8) == 0
+    assert native.mg_syr2k_workspace_size(0, 2 ** 40, 8) == 0
+    with pytest.raises(native.MgemmError):
+        native.mg_fp8_packed_size(2 ** 40, 128)
+    with pytest.raises(native.MgemmError):
+        native.mg_i8_packed_size(128, 2 ** 40)
