@@ -93,7 +93,24 @@ def time_path(path, A, B, C, steps, warmup, torch, native):
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     total_ms = ev[0].elapsed_time(ev[steps])
     return {"ms_per_step": total_ms / steps, "kernel_ms_mean": float(np.mean(per)),
-            "kernel_ms_median": float(np.median(per)), "wall_s": wall}
+            "kernel_ms_median": float(np.median(per)), "kernel_ms_ci95": ci95(per), "wall_s": wall}
+
+
+def ci95(samples):
+    """95 % confidence interval of the mean of per-step times (Student t), the
+    statistic the paper reports over its repeated runs; None below 2 samples."""
+    n = len(samples)
+    if n < 2:
+        return None
+    m = float(np.mean(samples))
+    sd = float(np.std(samples, ddof=1))
+    try:
+        from scipy.stats import t as student_t
+        q = float(student_t.ppf(0.975, n - 1))
+    except ImportError:
+        q = 1.96
+    h = q * sd / np.sqrt(n)
+    return [round(float(m - h), 5), round(float(m + h), 5)]
 
 
 def single_result(path, A, B, C0_dev, torch, native):
@@ -232,6 +249,8 @@ def main():
                      "kernel_ms_mean": round(f32["kernel_ms_mean"], 4),
                      "algorithmic_flops_per_launch": flops},
     }
+    out["step_time_ms"] = {p: {"median": round(r["kernel_ms_median"], 5), "mean": round(r["kernel_ms_mean"], 5),
+                               "ci95": r["kernel_ms_ci95"]} for p, r in results.items()}
     if "bf16x3" in results:
         b = results["bf16x3"]
         out["bf16x3"] = {"tflops": round(b["tflops"], 2), "ms_per_step": round(b["ms_per_step"], 4),

@@ -97,19 +97,46 @@ hipError_t launch_syr2k(int cfg, bool lower, bool tr, int splits, GemmArgs g, hi
 }
 
 // C = alpha * (P_0 + ... + P_{S-1}) + beta * C0 on one triangle, partials
-// summed in order of s.  One workgroup row of threads per matrix row.
+// summed in order of s.  One workgroup per matrix row (grid-stride); each
+// thread takes four consecutive columns, with 16-byte accesses where all four
+// lie in the triangle and C allows them (vec_c: C 16-byte aligned, ldc % 4 ==
+// 0; the partials always do: 256-byte aligned base, ldp and the partial
+// stride multiples of 4), element by element otherwise.
 __global__ __launch_bounds__(256) void syr2k_reduce_kernel(const float* __restrict__ part, int64_t ldp,
                                                           int64_t stride, int S, float* C, int64_t N,
-                                                          int64_t ldc, float alpha, float beta, int lower)
+                                                          int64_t ldc, float alpha, float beta, int lower,
+                                                          int vec_c)
 {
     for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
         const int64_t j0 = lower ? 0 : i, j1 = lower ? i + 1 : N;
-        for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-            const float* p = part + i * ldp + j;
-            float acc = p[0];
-            for (int s = 1; s < S; ++s) acc += p[s * stride];
-            float* c = C + i * ldc + j;
-            *c = beta != 0.f ? __builtin_fmaf(alpha, acc, beta * *c) : alpha * acc;
+        for (int64_t q = (j0 & ~int64_t(3)) + 4 * int64_t(threadIdx.x); q < j1; q += 4 * int64_t(blockDim.x)) {
+            const float* p = part + i * ldp + q;
+            float* c = C + i * ldc + q;
+            if (vec_c && q >= j0 && q + 3 < j1) {
+                floatx4 acc = *reinterpret_cast<const floatx4*>(p);
+                for (int s = 1; s < S; ++s) {
+                    const floatx4 v = *reinterpret_cast<const floatx4*>(p + s * stride);
+                    acc[0] += v[0]; acc[1] += v[1]; acc[2] += v[2]; acc[3] += v[3];
+                }
+                floatx4 o;
+                if (beta != 0.f) {
+                    const floatx4 c0 = *reinterpret_cast<const floatx4*>(c);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = __builtin_fmaf(alpha, acc[e], beta * c0[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = alpha * acc[e];
+                }
+                *reinterpret_cast<floatx4*>(c) = o;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (q + e < j0 || q + e >= j1) continue;
+                    float acc = p[e];
+                    for (int s = 1; s < S; ++s) acc += p[s * stride + e];
+                    c[e] = beta != 0.f ? __builtin_fmaf(alpha, acc, beta * c[e]) : alpha * acc;
+                }
+            }
         }
     }
 }
@@ -118,7 +145,7 @@ hipError_t launch_syr2k_reduce(const GemmArgs& g, int splits, bool lower, hipStr
 {
     const int64_t blocks = g.N < 8192 ? g.N : 8192;
     hipLaunchKernelGGL(syr2k_reduce_kernel, dim3(unsigned(blocks > 0 ? blocks : 1)), dim3(256), 0, stream, g.part,
-                       g.ldp, g.part_stride, splits, g.C, g.N, g.ldc, g.alpha, g.beta, int(lower));
+                       g.ldp, g.part_stride, splits, g.C, g.N, g.ldc, g.alpha, g.beta, int(lower), int(g.vec_c));
     return hipGetLastError();
 }
 
