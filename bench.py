@@ -731,7 +731,7 @@ def bench_types(args, torch, si, native, dev):
                       "int8_inputs": "uniform integers in [-128, 127]"},
            "roofline": {"bound": "mfma", "achieved": rows["int8_gemm_only"]["tops"], "peak": INT8_PEAK_TOPS,
                         "unit": "TOP/s", "frac": rows["int8_gemm_only"]["frac_of_int8_peak"], "traffic": None,
-                        "kernel": "gemm_i8_kernel<256,256,128,64,interleaved>"},
+                        "kernel": "gemm_i8_direct_kernel<256,256,128,64>"},
            "rows": rows}
     print(json.dumps(out), flush=True)
 

@@ -342,6 +342,136 @@ static hipError_t launch_fp8_cfg(Fp8Args g, hipStream_t stream)
     return hipGetLastError();
 }
 
+// Direct form (direct_copy in tile_bytes.h): the next panel is copied from
+// global memory straight into LDS while the current one is multiplied, with
+// no register staging and no LDS write instructions.  The two buffers are
+// separate arrays used in a fixed alternation, so the compiler can tell the
+// copy into one from the reads of the other.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_fp8_direct_kernel(Fp8Args g)
+{
+    constexpr int BK = 128;                 // one scale block per K-panel
+    constexpr int STEPS = BK / 64;
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NW = (BM / WM) * WAVES_N;
+    constexpr int V = WM / 32, H = WN / 32;
+
+    __shared__ __attribute__((aligned(1024))) uint8_t A0[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t A1[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t B0[BN * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t B1[BN * BK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int nk = int(g.Kp / BK);
+    int srow_a[V], srow_b[H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+        srow_a[i] = __builtin_amdgcn_readfirstlane(int((m0 + wm0 + 32 * i) / 128 * g.lds));
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+        srow_b[j] = __builtin_amdgcn_readfirstlane(int((n0 + wn0 + 32 * j) / 128 * g.lds));
+    int sa[V], sb[H], sa_n[V], sb_n[H];
+#pragma unroll
+    for (int i = 0; i < V; ++i) sa[i] = g.sA[srow_a[i]];
+#pragma unroll
+    for (int j = 0; j < H; ++j) sb[j] = g.sB[srow_b[j]];
+    auto next_scales = [&](int kn) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) sa_n[i] = g.sA[srow_a[i] + kn];
+#pragma unroll
+        for (int j = 0; j < H; ++j) sb_n[j] = g.sB[srow_b[j] + kn];
+    };
+    auto take_scales = [&]() {
+#pragma unroll
+        for (int i = 0; i < V; ++i) sa[i] = sa_n[i];
+#pragma unroll
+        for (int j = 0; j < H; ++j) sb[j] = sb_n[j];
+    };
+
+    const uint8_t* __restrict__ qa = g.qA + m0 * g.ldq;
+    const uint8_t* __restrict__ qb = g.qB + n0 * g.ldq;
+    const uint32_t ld32 = uint32_t(g.ldq);
+    auto copy_panel = [&](uint8_t* LA, uint8_t* LB, int kp) {
+        direct_copy<BM, NW>(qa, ld32, uint32_t(kp) * BK, LA, wave, lane);
+        direct_copy<BN, NW>(qb, ld32, uint32_t(kp) * BK, LB, wave, lane);
+    };
+    auto frag = [&](const uint8_t* L, int row, int s) {
+        const int g0 = 4 * s + 2 * h;        // global chunks g0, g0 + 1 of the row
+        const uint4 lo = direct_chunk(L, row, g0), hi = direct_chunk(L, row, g0 + 1);
+        return intx8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+    };
+    auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            intx8 a[V], b[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i) a[i] = frag(LA, wm0 + 32 * i + c, s);
+#pragma unroll
+            for (int j = 0; j < H; ++j) b[j] = frag(LB, wn0 + 32 * j + c, s);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
+        }
+    };
+    // all copies landed in LDS, then every wave past the barrier
+    auto arrive = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
+    copy_panel(A0, B0, 0);
+    arrive();
+    for (int kt = 0; kt < nk; kt += 2) {
+        // panel kt in buffer 0; panel kt+1 is copied into buffer 1 meanwhile
+        if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
+        next_scales(kt + 1 < nk ? kt + 1 : kt);
+        panel(A0, B0);
+        take_scales();
+        arrive();
+        if (kt + 1 < nk) {
+            if (kt + 2 < nk) copy_panel(A0, B0, kt + 2);
+            next_scales(kt + 2 < nk ? kt + 2 : kt + 1);
+            panel(A1, B1);
+            take_scales();
+            arrive();
+        }
+    }
+
+    const float alpha = g.alpha, beta = g.beta;
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_fp8_direct(Fp8Args g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_fp8_direct_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    return hipGetLastError();
+}
+
 const SgemmConfig kFp8Configs[] = {
     // id, BM, BN, BK, WM, WN
     {0, 256, 256, 128, 128, 128},
@@ -351,6 +481,8 @@ const SgemmConfig kFp8Configs[] = {
     {4, 256, 256, 128, 128, 64},
     {5, 256, 256, 128, 128, 64},   // packs interleaved with the matrix work
     {6, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
+    {7, 256, 256, 128, 128, 64},   // panels copied straight into LDS
+    {8, 128, 128, 128, 64, 64},    // panels copied straight into LDS
 };
 const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
 
@@ -364,6 +496,8 @@ hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
     case 4: return launch_fp8_cfg<256, 256, 128, 64, false>(g, stream);
     case 5: return launch_fp8_cfg<256, 256, 128, 64, true>(g, stream);
     case 6: return launch_fp8_cfg<128, 128, 64, 64, true>(g, stream);
+    case 7: return launch_fp8_direct<256, 256, 128, 64>(g, stream);
+    case 8: return launch_fp8_direct<128, 128, 64, 64>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -276,6 +276,103 @@ hipError_t launch_scale_c_i32(int32_t* C, int64_t M, int64_t N, int64_t ldc, int
     return hipGetLastError();
 }
 
+// Direct form (direct_copy in tile_bytes.h): the next panel is copied from
+// global memory straight into LDS while the current one is multiplied, with
+// no register staging and no LDS write instructions.  The two buffers are
+// separate arrays used in a fixed alternation, so the compiler can tell the
+// copy into one from the reads of the other.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_i8_direct_kernel(I8Args g)
+{
+    constexpr int BK = 128;
+    constexpr int STEPS = BK / 32;
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NW = (BM / WM) * WAVES_N;
+    constexpr int V = WM / 32, H = WN / 32;
+
+    __shared__ __attribute__((aligned(1024))) uint8_t A0[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t A1[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t B0[BN * BK];
+    __shared__ __attribute__((aligned(1024))) uint8_t B1[BN * BK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+    const uint8_t* __restrict__ qa = reinterpret_cast<const uint8_t*>(g.qA) + m0 * g.ldq;
+    const uint8_t* __restrict__ qb = reinterpret_cast<const uint8_t*>(g.qB) + n0 * g.ldq;
+    const uint32_t ld32 = uint32_t(g.ldq);
+
+    intx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+    auto copy_panel = [&](uint8_t* LA, uint8_t* LB, int kp) {
+        direct_copy<BM, NW>(qa, ld32, uint32_t(kp) * BK, LA, wave, lane);
+        direct_copy<BN, NW>(qb, ld32, uint32_t(kp) * BK, LB, wave, lane);
+    };
+    auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            // lane (c, h) supplies 16 k of row c: global chunk 2s + h
+            intx4 a[V], b[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i) a[i] = __builtin_bit_cast(intx4, direct_chunk(LA, wm0 + 32 * i + c, 2 * s + h));
+#pragma unroll
+            for (int j = 0; j < H; ++j) b[j] = __builtin_bit_cast(intx4, direct_chunk(LB, wn0 + 32 * j + c, 2 * s + h));
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    // all copies landed in LDS, then every wave past the barrier
+    auto arrive = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
+    const int nk = int(g.Kp / BK);
+    copy_panel(A0, B0, 0);
+    arrive();
+    for (int kt = 0; kt < nk; kt += 2) {
+        // panel kt in buffer 0; panel kt+1 is copied into buffer 1 meanwhile
+        if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
+        panel(A0, B0);
+        arrive();
+        if (kt + 1 < nk) {
+            if (kt + 2 < nk) copy_panel(A0, B0, kt + 2);
+            panel(A1, B1);
+            arrive();
+        }
+    }
+
+    // C = alpha*acc + beta*C0 modulo 2^32 (unsigned arithmetic wraps).
+    const uint32_t alpha = uint32_t(g.alpha), beta = uint32_t(g.beta);
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0u, acc,
+                           [&](int32_t a, int32_t c0) { return int32_t(alpha * uint32_t(a) + beta * uint32_t(c0)); });
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_i8_direct(I8Args g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_i8_direct_kernel<BM, BN, WM, WN>), dim3(g.tiles_m * g.tiles_n), dim3(NT), 0, stream, g);
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int WM, int WN, bool INTERLEAVE>
 static hipError_t launch_i8_cfg(I8Args g, hipStream_t stream)
 {
@@ -294,6 +391,7 @@ const SgemmConfig kI8Configs[] = {
     {2, 64, 64, 128, 32, 32},
     {3, 256, 256, 128, 128, 64},   // packs interleaved with the matrix work
     {4, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
+    {5, 256, 256, 128, 128, 64},   // panels copied straight into LDS
 };
 const int kNumI8Configs = sizeof(kI8Configs) / sizeof(kI8Configs[0]);
 
@@ -305,6 +403,7 @@ hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream)
     case 2: return launch_i8_cfg<64, 64, 32, 32, false>(g, stream);
     case 3: return launch_i8_cfg<256, 256, 128, 64, true>(g, stream);
     case 4: return launch_i8_cfg<128, 128, 64, 64, true>(g, stream);
+    case 5: return launch_i8_direct<256, 256, 128, 64>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

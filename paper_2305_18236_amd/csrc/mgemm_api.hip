@@ -163,14 +163,19 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
     const int64_t cus = device_cus();
     if (path == MG_PATH_FP8_T128) {
-        // interleaved-pack forms (5, 6): 2300 vs 1970 TFLOP/s at 8192^3
-        if (tiles(M, N, 256, 256) >= 256) return 5;
+        // 256 x 256: panels copied straight into LDS (7): 2359-2418 TFLOP/s
+        // at 8192^3 against 2200-2378 for the interleaved pack (5) and 1970
+        // for the plain loop (4); 128 x 128: the interleaved pack (6) beats
+        // the direct copy (8), 1904-1954 vs 1764-1839
+        if (tiles(M, N, 256, 256) >= 256) return 7;
         if (tiles(M, N, 128, 128) >= 128) return 6;
         return 3;
     }
     if (path == MG_CONFIGS_I8) {
-        // interleaved-pack forms (3, 4): 2170 vs 1870 TOP/s at 8192^3
-        if (tiles(M, N, 256, 256) >= 256) return 3;
+        // 256 x 256: panels copied straight into LDS (5): 2255 TOP/s at
+        // 8192^3 against 2128-2190 for the interleaved pack (3) and 1870 for
+        // the plain loop (0); 128 x 128: the interleaved pack (4)
+        if (tiles(M, N, 256, 256) >= 256) return 5;
         if (tiles(M, N, 128, 128) >= 128) return 4;
         return 2;
     }

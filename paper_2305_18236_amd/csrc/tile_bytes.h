@@ -41,4 +41,35 @@ struct BytePanel {
     }
 };
 
+// Direct form of the byte panels: packed 128-byte k rows copied from global
+// memory straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes land
+// at the wave's LDS base + 16 * lane), with no register staging and no LDS
+// write instructions.  LDS rows are unpadded; since the copy cannot scatter,
+// the bank-conflict-free layout is made by choosing the source instead: LDS
+// chunk c of row r holds global chunk c ^ direct_swz(r), so 16 consecutive
+// rows read at one k fall on 16 distinct 16-byte bank groups.
+MG_DEVICE int direct_swz(int r) { return (r >> 1) & 7; }
+
+// Copy ROWS rows of 128 bytes (row stride ld32 from q, k offset k0) into
+// `lds`; copy j of wave w fills LDS chunks (j*NW + w)*64 .. +63.
+template <int ROWS, int NW>
+MG_DEVICE void direct_copy(const uint8_t* __restrict__ q, uint32_t ld32, uint32_t k0, uint8_t* lds, int wave,
+                           int lane)
+{
+    constexpr int J = ROWS * 8 / (NW * 64);
+    static_assert(ROWS * 8 % (NW * 64) == 0, "panels must split evenly");
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int slot = (j * NW + wave) * 64 + lane, r = slot >> 3;
+        const uint32_t off = uint32_t(r) * ld32 + k0 + 16u * uint32_t((slot & 7) ^ direct_swz(r));
+        __builtin_amdgcn_global_load_lds(q + off, lds + (j * NW + wave) * 1024, 16, 0, 0);
+    }
+}
+
+// The 16 bytes of global chunk g (k bytes 16g .. 16g+15) of LDS row `row`.
+MG_DEVICE uint4 direct_chunk(const uint8_t* lds, int row, int g)
+{
+    return *reinterpret_cast<const uint4*>(lds + row * 128 + 16 * (g ^ direct_swz(row)));
+}
+
 }  // namespace mg
