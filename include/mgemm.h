@@ -42,7 +42,11 @@
  *   MG_ERR_TOO_LARGE.  For such a dimension the query functions answer
  *   without computing: the *_workspace_size functions return 0,
  *   mg_split_count 1, and mg_tuned_config, mg_batched_config,
- *   mg_fp8_packed_size and mg_i8_packed_size MG_ERR_TOO_LARGE.
+ *   mg_fp8_packed_size and mg_i8_packed_size MG_ERR_TOO_LARGE.  The FP8
+ *   GEMMs (mg_gemm with MG_PATH_FP8_T128, mg_gemm_fp8_packed) take K up to
+ *   2^23 = 8388608 and return MG_ERR_TOO_LARGE beyond it (their kernels
+ *   address a 256-row panel with 32-bit offsets); mg_gemm_workspace_size
+ *   returns 0 there.  INT8 takes K up to 131071 (see mg_gemm_i8).
  */
 #ifndef MGEMM_H
 #define MGEMM_H

@@ -211,6 +211,9 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
 int pick_config(int path, int64_t M, int64_t N, int64_t K);
 
 // ---- FP8 packed layout: q is Rp x Kp bytes, scales (Rp/128) x (Kp/128) bytes.
+// The GEMM kernels address a 256-row panel of q with 32-bit byte offsets, so
+// K is limited to 2^23 (256 rows x 2^23 bytes = 2^31).
+constexpr int64_t kMaxFp8K = int64_t(1) << 23;
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 int64_t fp8_rows(int64_t R) { return round_up(R > 0 ? R : 1, 256); }
 int64_t fp8_kp(int64_t K) { return round_up(K > 0 ? K : 1, 128); }
@@ -241,9 +244,15 @@ Fp8Workspace fp8_workspace(int64_t M, int64_t N, int64_t K)
 // bf16x3 the packed operands are as large as the FP32 ones and the in-kernel
 // conversion hides behind the matrix core (about 370 vs 347 TFLOP/s), so
 // bf16x3 converts in the kernel.
+// The packed-operand kernels address a 256-row panel with 32-bit byte
+// offsets (row * row stride), so the pre-packed planes are used only while
+// 256 rows of 2-byte elements stay below 2^31 bytes; longer K converts in the
+// kernel, whose loads fall back to 64-bit addressing.
+constexpr int64_t kMaxPrepackK = int64_t(1) << 22;
+
 bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 {
-    return (path == MG_PATH_BF16 || path == MG_PATH_FP16) && M >= 512 && N >= 512 && K >= 32;
+    return (path == MG_PATH_BF16 || path == MG_PATH_FP16) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
 }
 
 struct Bf16Workspace {
@@ -540,6 +549,7 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
     if (!float_path(path)) return MG_ERR_UNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (path == MG_PATH_FP8_T128) {
+        if (K > kMaxFp8K) return MG_ERR_TOO_LARGE;
         const size_t need = fp8_workspace(M, N, K).total;
         if (M > 0 && N > 0 && K > 0 && alpha != 0.f &&
             (workspace == nullptr || workspace_bytes < need ||
@@ -594,7 +604,7 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int
 {
     (void)transA; (void)transB;
     if (M <= 0 || N <= 0 || K <= 0 || !float_path(path) || beyond_int(M, N, K)) return 0;
-    if (path == MG_PATH_FP8_T128) return fp8_workspace(M, N, K).total;
+    if (path == MG_PATH_FP8_T128) return K > kMaxFp8K ? 0 : fp8_workspace(M, N, K).total;
     size_t total = 0;
     if (is_16bit(path) && bf16_prepack_pays(path, M, N, K))
         total += align256(bf16_workspace(path, M, N, K).total);
@@ -638,7 +648,7 @@ int mg_gemm_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8
     if (qB == nullptr || sB == nullptr) return -7;
     if (C == nullptr && M > 0 && N > 0) return -10;
     if (ldc < (N > 1 ? N : 1) || !fits(M, ldc)) return -11;
-    if (M > INT_MAX || N > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    if (M > INT_MAX || N > INT_MAX || K > kMaxFp8K) return MG_ERR_TOO_LARGE;
     if ((reinterpret_cast<uintptr_t>(qA) & 15) || (reinterpret_cast<uintptr_t>(qB) & 15)) return -5;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (M == 0 || N == 0) return MG_OK;

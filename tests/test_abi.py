@@ -180,3 +180,14 @@ def test_queries_on_empty_and_huge_shapes(native):
         native.mg_fp8_packed_size(2 ** 40, 128)
     with pytest.raises(native.MgemmError):
         native.mg_i8_packed_size(128, 2 ** 40)
+
+
+def test_fp8_k_limit_is_checked_on_the_host(native):
+    """The FP8 GEMM kernels address a 256-row panel with 32-bit offsets, so
+    K above 2^23 is refused before any device call (the pointers here are
+    never dereferenced), and the workspace query answers 0 there."""
+    fake, K = 0x1000, 2 ** 23 + 1
+    assert native.mg_gemm_workspace_size(3, "N", "N", 8, 8, K) == 0
+    assert native.mg_gemm_workspace_size(3, "N", "N", 8, 8, K - 1) > 0
+    assert native.mg_gemm(3, "N", "N", 8, 8, K, 1.0, fake, K, fake, 8, 0.0, fake, 8, fake, 1 << 40, None) == -102
+    assert native.mg_gemm_fp8_packed(8, 8, K, 1.0, fake, fake, fake, fake, 0.0, fake, 8, None) == -102
