@@ -1,6 +1,7 @@
 // BF16 and bf16x3 GEMM kernels and launchers: one workgroup per output tile
 // of the scheme in tile_bf16.h, plus the stand-alone pack-stage conversion.
 #include "tile_bf16.h"
+#include "tile_bytes.h"
 #include "kernels.h"
 
 namespace mg {
@@ -31,6 +32,110 @@ void gemm_bf16_packed_kernel(GemmArgs args)
     bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS, true>(g, tm, tn, smem);
 }
 
+// Direct form on pre-packed single-term planes (direct_copy in tile_bytes.h):
+// each 64-deep K panel of op(A) and op(B)^T is 128 bytes per row, copied from
+// the planes straight into LDS while the previous panel is multiplied, with
+// no register staging and no LDS write instructions.  The two buffers are
+// separate arrays used in a fixed alternation, so the compiler can tell the
+// copy into one from the reads of the other.  The planes are zero-padded to
+// whole 256-row tiles and 128-deep K grains, so every copy is in bounds and
+// the padding adds zeros.
+template <int BM, int BN, int WM, int WN, int TERMS>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_bf16_direct_kernel(GemmArgs args)
+{
+    static_assert(TERMS != 3, "the direct form multiplies single-term planes");
+    constexpr int BK = 64;                    // bf16 elements per panel row (128 bytes)
+    constexpr int STEPS = BK / 16;
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NW = (BM / WM) * WAVES_N;
+    constexpr int V = WM / 32, H = WN / 32;
+
+    __shared__ __attribute__((aligned(1024))) uint8_t A0[BM * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t A1[BM * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t B0[BN * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t B1[BN * 128];
+
+    GemmArgs g = args;
+    split_k_view<false, true, true>(g);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+    const uint8_t* __restrict__ qa = reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda);
+    const uint8_t* __restrict__ qb = reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb);
+    const uint32_t lda32 = uint32_t(2 * g.lda), ldb32 = uint32_t(2 * g.ldb);
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto copy_panel = [&](uint8_t* LA, uint8_t* LB, int kp) {
+        direct_copy<BM, NW>(qa, lda32, uint32_t(kp) * 128u, LA, wave, lane);
+        direct_copy<BN, NW>(qb, ldb32, uint32_t(kp) * 128u, LB, wave, lane);
+    };
+    auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            // lane (c, h) supplies k 16s + 8h .. +7 of row c: global chunk 2s + h
+            bf16x8 a[V], b[H];
+#pragma unroll
+            for (int i = 0; i < V; ++i) a[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 2 * s + h));
+#pragma unroll
+            for (int j = 0; j < H; ++j) b[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 2 * s + h));
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<TERMS>(a[i], b[j], acc[i][j]);
+        }
+    };
+    // all copies landed in LDS, then every wave past the barrier
+    auto arrive = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
+    const int nk = int((g.K + BK - 1) / BK);
+    if (nk > 0) {
+        copy_panel(A0, B0, 0);
+        arrive();
+    }
+    for (int kt = 0; kt < nk; kt += 2) {
+        // panel kt in buffer 0; panel kt+1 is copied into buffer 1 meanwhile
+        if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
+        panel(A0, B0);
+        arrive();
+        if (kt + 1 < nk) {
+            if (kt + 2 < nk) copy_panel(A0, B0, kt + 2);
+            panel(A1, B1);
+            arrive();
+        }
+    }
+
+    const float alpha = g.alpha, beta = g.beta;
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
+}
+
+template <int BM, int BN, int WM, int WN, int TERMS>
+static hipError_t launch_bf16_direct(GemmArgs g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
+    hipLaunchKernelGGL((gemm_bf16_direct_kernel<BM, BN, WM, WN, TERMS>), grid, block, 0, stream, g);
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WM, int WN, int TERMS>
 static hipError_t launch_bf16_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stream, bool packed)
 {
@@ -54,6 +159,9 @@ const SgemmConfig kBf16Configs[] = {
     {3, 256, 128, 32, 128, 64},
     {4, 64, 64, 32, 32, 32},
     {5, 128, 64, 32, 64, 32},
+    // configuration 1's tiles with panels copied straight into LDS, on
+    // pre-packed single-term planes; elsewhere it runs as configuration 1
+    {6, 256, 256, 64, 128, 64},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
@@ -67,6 +175,10 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 3: return launch_bf16_cfg<256, 128, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
     case 4: return launch_bf16_cfg<64, 64, 32, 32, 32, TERMS>(ta, tb, g, stream, packed);
     case 5: return launch_bf16_cfg<128, 64, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
+    case 6:
+        if constexpr (TERMS != 3)
+            if (packed) return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
+        return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }

@@ -159,6 +159,8 @@ int auto_splits(int64_t t, int64_t K)
 // 256 x 256 tiles and 398 us with 64 x 64).  The 16-bit paths keep the
 // ladder there (bf16x3 at the same shape: 222 us with 256 x 256 tiles, 303 us
 // with 64 x 64).
+bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K);
+
 int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
     const int64_t cus = device_cus();
@@ -203,6 +205,12 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
             const mg::SgemmConfig& d = t.cfgs[ladder[i + 1]];
             if (tiles(M, N, d.bm, d.bn) >= cus) return ladder[i + 1];
         }
+        // BF16 / FP16 on pre-packed planes: the same 256 x 256 tiles with
+        // panels copied straight into LDS (6), bit-identical to (1) and
+        // faster (8192^3 end to end: BF16 1078-1080 against 975-997
+        // TFLOP/s, FP16 1023-1030 against 941-948).  Without the planes'
+        // workspace configuration 6 runs as configuration 1.
+        if (ladder[i] == 1 && bf16_prepack_pays(path, M, N, K)) return 6;
         return ladder[i];
     }
     return ladder[2];

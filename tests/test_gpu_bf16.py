@@ -105,7 +105,7 @@ def test_ragged_shapes_all_layouts(gpu, path, tA, tB, M, N, K):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, path, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, path, cfg=cfg)
@@ -123,7 +123,7 @@ def test_prepacked_and_in_kernel_conversion(gpu, path, tA, tB, use_workspace):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
 def test_prepacked_every_config(gpu, path, cfg):
     _check(Problem(777, 531, 203, "T", "N", -1.0, 0.25, seed=100 + cfg), gpu, path, cfg=cfg)
 
@@ -192,3 +192,34 @@ def test_full_size_8192_sampled(gpu, path, dist):
     err = oracle.normalized_error(C[I, J], cref, d)
     print(f"{path} {dist} 8192^3 sampled normalised error {err:.3e}")
     assert err <= TOL[path], err
+
+
+@pytest.mark.parametrize("path", ["bf16", "fp16"])
+@pytest.mark.parametrize("M,N,K,tA,tB,splits", [
+    (512, 512, 32, "N", "N", -1), (777, 531, 203, "T", "N", -1), (600, 1030, 1500, "N", "T", 3),
+    (513, 700, 129, "T", "T", -1), (1024, 768, 4096, "N", "N", 5)])
+def test_direct_copy_equals_staged_kernel_bitwise(gpu, path, M, N, K, tA, tB, splits):
+    """Configuration 6 copies the pre-packed planes' 64-deep panels straight
+    into LDS; its MFMA sequence over k is configuration 1's, so the two
+    results must agree bit for bit (ragged tiles, ragged K, split K ranges),
+    and both must meet the path's bound against the oracle."""
+    nat = _native()
+    pid = {"bf16": 2, "fp16": 4}[path]
+    outs = []
+    for cfg in (1, 6):
+        p = Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + N + K)
+        assert nat.mg_force_config(pid, cfg) == 0
+        if splits > 0:
+            assert nat.mg_force_splits(pid, splits) == 0
+        try:
+            p.to_device(gpu)
+            st = p.run(path)
+            assert st == 0, nat.status_string(st)
+            outs.append(p.result())
+        finally:
+            nat.mg_force_config(pid, -1)
+            nat.mg_force_splits(pid, -1)
+        assert p.padding_untouched()
+    assert np.array_equal(outs[0], outs[1])
+    Cref, D = p.oracle()
+    assert oracle.normalized_error(outs[1], Cref, D) <= tolerance(path, K)

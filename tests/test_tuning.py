@@ -154,3 +154,15 @@ def test_split_plan_rules(native):
     # one tile and a long K splits into ranges at least 256 deep
     s = native.mg_split_count(0, 64, 64, 4096)
     assert 2 <= s <= 16 and 4096 / s >= 256 - 128
+
+
+def test_sixteen_bit_direct_copy_choice(native):
+    """BF16 and FP16 problems large enough for the pre-packed planes and for
+    256 x 256 tiles take configuration 6 (the same tiles, panels copied
+    straight into LDS); bf16x3, which converts in the kernel, and problems
+    too small to pre-pack keep configuration 1."""
+    for path in (2, 4):
+        assert native.mg_tuned_config(path, 8192, 8192, 8192) == 6
+        assert native.mg_tuned_config(path, 256, 8192, 8192) == 1          # M < 512: no planes
+        assert native.mg_tuned_config(path, 8192, 8192, 2 ** 22 + 1) == 1  # beyond the planes' K limit
+    assert native.mg_tuned_config(1, 8192, 8192, 8192) == 1
