@@ -125,6 +125,132 @@ void gemm_bf16_direct_kernel(GemmArgs args)
                            [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
 }
 
+// bf16x3 direct form on the interleaved planes (launch_bf16_pack_interleaved):
+// a 32-deep panel of both terms is one 128-byte row (hi in global chunks
+// 0-3, lo in 4-7), copied straight into LDS as in the single-term kernel.
+// Per 16-deep step the three products are issued in the in-kernel
+// conversion's order (lo(A) hi(B), hi(A) lo(B), hi(A) hi(B)), so the result
+// is bit-identical to it.  Split K: workgroup row s takes the K range
+// [s k_chunk, ...), 4 bytes per k in these rows.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void gemm_bf16x3_direct_kernel(GemmArgs args)
+{
+    constexpr int BK = 32;
+    constexpr int STEPS = BK / 16;
+    constexpr int WAVES_N = BN / WN;
+    constexpr int NW = (BM / WM) * WAVES_N;
+    constexpr int V = WM / 32, H = WN / 32;
+
+    __shared__ __attribute__((aligned(1024))) uint8_t A0[BM * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t A1[BM * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t B0[BN * 128];
+    __shared__ __attribute__((aligned(1024))) uint8_t B1[BN * 128];
+
+    GemmArgs g = args;
+    int64_t kbyte0 = 0;
+    if (gridDim.y > 1) {
+        const int64_t k0 = int64_t(blockIdx.y) * g.k_chunk;
+        g.K = min(g.k_chunk, g.K - k0);
+        kbyte0 = 4 * k0;
+        g.C = g.part + int64_t(blockIdx.y) * g.part_stride;
+        g.ldc = g.ldp;
+        g.alpha = 1.f;
+        g.beta = 0.f;
+    }
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+    const int c = lane & 31, h = lane >> 5;
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+    const uint8_t* __restrict__ qa =
+        reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda) + kbyte0;
+    const uint8_t* __restrict__ qb =
+        reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb) + kbyte0;
+    const uint32_t lda32 = uint32_t(2 * g.lda), ldb32 = uint32_t(2 * g.ldb);
+
+    floatx16 acc[V][H];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto copy_panel = [&](uint8_t* LA, uint8_t* LB, int kp) {
+        direct_copy<BM, NW>(qa, lda32, uint32_t(kp) * 128u, LA, wave, lane);
+        direct_copy<BN, NW>(qb, ldb32, uint32_t(kp) * 128u, LB, wave, lane);
+    };
+    auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            // lane (c, h) supplies k 16s + 8h .. +7 of row c: hi in global
+            // chunk 2s + h, lo in chunk 4 + 2s + h
+            bf16x8 ah[V], al[V], bh[H], bl[H];
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                bh[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 2 * s + h));
+                bl[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 4 + 2 * s + h));
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                ah[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 2 * s + h));
+                al[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 4 + 2 * s + h));
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(al[i], bh[j], acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bh[j], acc[i][j]);
+        }
+    };
+    auto arrive = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
+    const int nk = int((g.K + BK - 1) / BK);
+    if (nk > 0) {
+        copy_panel(A0, B0, 0);
+        arrive();
+    }
+    for (int kt = 0; kt < nk; kt += 2) {
+        if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
+        panel(A0, B0);
+        arrive();
+        if (kt + 1 < nk) {
+            if (kt + 2 < nk) copy_panel(A0, B0, kt + 2);
+            panel(A1, B1);
+            arrive();
+        }
+    }
+
+    const float alpha = g.alpha, beta = g.beta;
+    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
+                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_bf16x3_direct(GemmArgs g, hipStream_t stream)
+{
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    g.tiles_m = int((g.M + BM - 1) / BM);
+    g.tiles_n = int((g.N + BN - 1) / BN);
+    const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
+    hipLaunchKernelGGL((gemm_bf16x3_direct_kernel<BM, BN, WM, WN>), grid, block, 0, stream, g);
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int WM, int WN, int TERMS>
 static hipError_t launch_bf16_direct(GemmArgs g, hipStream_t stream)
 {
@@ -160,7 +286,8 @@ const SgemmConfig kBf16Configs[] = {
     {4, 64, 64, 32, 32, 32},
     {5, 128, 64, 32, 64, 32},
     // configuration 1's tiles with panels copied straight into LDS, on
-    // pre-packed single-term planes; elsewhere it runs as configuration 1
+    // pre-packed planes (bf16x3: the interleaved ones); without the planes
+    // it runs as configuration 1
     {6, 256, 256, 64, 128, 64},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
@@ -176,8 +303,10 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 4: return launch_bf16_cfg<64, 64, 32, 32, 32, TERMS>(ta, tb, g, stream, packed);
     case 5: return launch_bf16_cfg<128, 64, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
     case 6:
-        if constexpr (TERMS != 3)
-            if (packed) return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
+        if (packed) {
+            if constexpr (TERMS == 3) return launch_bf16x3_direct<256, 256, 128, 64>(g, stream);
+            else return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
+        }
         return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
@@ -211,11 +340,15 @@ constexpr int PROW = PT + 8;     // LDS row of the pack tile (bf16), T == false
 // eight to a bank).  Returns the element offset of element k of row r.
 MG_DEVICE int pt_swizzle(int r, int k) { return 8 * (((k >> 3) ^ (r >> 2)) & 15) + (k & 7); }
 
-template <bool T, int TERMS>
+// IL (bf16x3 only): one plane whose rows interleave the two terms per 32 k,
+// hi(k0 .. k0+31) then lo(k0 .. k0+31), so that a 32-deep panel of both
+// terms is one 128-byte row (row stride ldq = 2 Kp elements; `lo` unused).
+template <bool T, int TERMS, bool IL = false>
 __global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict__ X, int64_t ldx, int64_t R,
                                                         int64_t Kd, int vec, uint16_t* __restrict__ hi,
                                                         uint16_t* __restrict__ lo, int64_t ldq)
 {
+    static_assert(!IL || TERMS == 3, "interleaving needs two terms");
     constexpr int ROW = T ? PT : PROW;
     __shared__ __attribute__((aligned(16))) uint16_t th[PT * ROW];
     __shared__ __attribute__((aligned(16))) uint16_t tl[TERMS == 3 ? PT * ROW : 8];
@@ -281,9 +414,17 @@ __global__ __launch_bounds__(256) void bf16_pack_kernel(const float* __restrict_
         const int id = tid + 256 * s;
         const int r = id / 16, c = 8 * (id % 16);
         const int off = T ? r * PT + pt_swizzle(r, c) : r * PROW + c;
-        *reinterpret_cast<uint4*>(hi + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&th[off]);
-        if (TERMS == 3)
-            *reinterpret_cast<uint4*>(lo + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tl[off]);
+        if constexpr (IL) {
+            // k = k0 + c .. +7 lies inside one 32-k group (c % 8 == 0)
+            const int64_t k = k0 + c;
+            uint16_t* dst = hi + (r0 + r) * ldq + 64 * (k >> 5) + (k & 31);
+            *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&th[off]);
+            *reinterpret_cast<uint4*>(dst + 32) = *reinterpret_cast<const uint4*>(&tl[off]);
+        } else {
+            *reinterpret_cast<uint4*>(hi + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&th[off]);
+            if (TERMS == 3)
+                *reinterpret_cast<uint4*>(lo + (r0 + r) * ldq + k0 + c) = *reinterpret_cast<const uint4*>(&tl[off]);
+        }
     }
 }
 
@@ -307,6 +448,17 @@ hipError_t launch_bf16_pack(bool trans, int terms, const float* X, int64_t ldx, 
         break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// bf16x3 pack into one plane per operand with the two terms interleaved per
+// 32 k (row stride ldq = 2 Kp elements).
+hipError_t launch_bf16_pack_interleaved(bool trans, const float* X, int64_t ldx, int64_t R, int64_t Kd, bool vec,
+                                        uint16_t* q, int64_t ldq, int64_t Rp, int64_t Kp, hipStream_t stream)
+{
+    const dim3 grid(unsigned(trans ? Rp / PT : Kp / PT), unsigned(trans ? Kp / PT : Rp / PT)), block(256);
+    if (trans) hipLaunchKernelGGL((bf16_pack_kernel<true, 3, true>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, nullptr, ldq);
+    else hipLaunchKernelGGL((bf16_pack_kernel<false, 3, true>), grid, block, 0, stream, X, ldx, R, Kd, int(vec), q, nullptr, ldq);
     return hipGetLastError();
 }
 

@@ -25,12 +25,16 @@ extern const SgemmConfig kBf16Configs[];
 extern const int kNumBf16Configs;
 
 // terms == 1: plain BF16; terms == 3: bf16x3 split.  packed: g.A / g.B are
-// the hi planes written by launch_bf16_pack (plane_a / plane_b to the lo planes).
+// the hi planes written by launch_bf16_pack (plane_a / plane_b to the lo
+// planes), or, for bf16x3 with configuration 6, the interleaved planes
+// written by launch_bf16_pack_interleaved (row stride lda / ldb = 2 Kp).
 hipError_t launch_gemm_bf16(int terms, int cfg, bool ta, bool tb, GemmArgs g, hipStream_t stream,
                             bool packed = false);
 hipError_t launch_bf16_pack(bool trans, int terms, const float* X, int64_t ldx, int64_t R, int64_t Kd,
                             bool vec, uint16_t* hi, uint16_t* lo, int64_t ldq, int64_t Rp, int64_t Kp,
                             hipStream_t stream);
+hipError_t launch_bf16_pack_interleaved(bool trans, const float* X, int64_t ldx, int64_t R, int64_t Kd, bool vec,
+                                        uint16_t* q, int64_t ldq, int64_t Rp, int64_t Kp, hipStream_t stream);
 hipError_t launch_bf16_split(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
 
 extern const SgemmConfig kFp8Configs[];

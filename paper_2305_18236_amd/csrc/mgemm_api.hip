@@ -159,7 +159,7 @@ int auto_splits(int64_t t, int64_t K)
 // 256 x 256 tiles and 398 us with 64 x 64).  The 16-bit paths keep the
 // ladder there (bf16x3 at the same shape: 222 us with 256 x 256 tiles, 303 us
 // with 64 x 64).
-bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K);
+bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K);
 
 int choose_config(int path, int64_t M, int64_t N, int64_t K)
 {
@@ -205,12 +205,14 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
             const mg::SgemmConfig& d = t.cfgs[ladder[i + 1]];
             if (tiles(M, N, d.bm, d.bn) >= cus) return ladder[i + 1];
         }
-        // BF16 / FP16 on pre-packed planes: the same 256 x 256 tiles with
+        // 16-bit paths on pre-packed planes: the same 256 x 256 tiles with
         // panels copied straight into LDS (6), bit-identical to (1) and
         // faster (8192^3 end to end: BF16 1078-1080 against 975-997
-        // TFLOP/s, FP16 1023-1030 against 941-948).  Without the planes'
+        // TFLOP/s, FP16 1023-1030 against 941-948, bf16x3 430-433 against
+        // 354-360; bf16x3 wins or ties at every shape measured where (1)
+        // is chosen, 8192 x 4096 x 256 to 8192^3).  Without the planes'
         // workspace configuration 6 runs as configuration 1.
-        if (ladder[i] == 1 && bf16_prepack_pays(path, M, N, K)) return 6;
+        if (ladder[i] == 1 && uses_planes(path, 6, M, N, K)) return 6;
         return ladder[i];
     }
     return ladder[2];
@@ -254,13 +256,25 @@ Fp8Workspace fp8_workspace(int64_t M, int64_t N, int64_t K)
 // bf16x3 converts in the kernel.
 // The packed-operand kernels address a 256-row panel with 32-bit byte
 // offsets (row * row stride), so the pre-packed planes are used only while
-// 256 rows of 2-byte elements stay below 2^31 bytes; longer K converts in the
-// kernel, whose loads fall back to 64-bit addressing.
-constexpr int64_t kMaxPrepackK = int64_t(1) << 22;
+// 256 rows of up to 4 bytes per k (bf16x3's interleaved terms) stay within
+// 2^31 bytes; longer K converts in the kernel, whose loads fall back to
+// 64-bit addressing.
+constexpr int64_t kMaxPrepackK = int64_t(1) << 21;
 
 bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 {
     return (path == MG_PATH_BF16 || path == MG_PATH_FP16) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+}
+
+// Whether configuration `cfg` of a 16-bit path multiplies pre-packed planes.
+// bf16x3 packs only for its direct form (6), into interleaved planes: with
+// the in-kernel conversion its packed operands would be as large as the
+// FP32 ones for no gain (about 347 against 370 TFLOP/s at 8192^3).
+bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K)
+{
+    if (path == MG_PATH_BF16X3)
+        return cfg == 6 && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+    return bf16_prepack_pays(path, M, N, K);
 }
 
 struct Bf16Workspace {
@@ -421,6 +435,20 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
         uint16_t* alo = reinterpret_cast<uint16_t*>(base + w.a_lo);
         uint16_t* bhi = reinterpret_cast<uint16_t*>(base + w.b_hi);
         uint16_t* blo = reinterpret_cast<uint16_t*>(base + w.b_lo);
+        if (terms == 3) {
+            // interleaved planes (configuration 6): A at a_hi, B at b_hi,
+            // 2 Kp elements per row, both terms in one plane
+            hipError_t e = mg::launch_bf16_pack_interleaved(ta, A, lda, M, K, fast_operand(A, lda), ahi, 2 * w.Kp,
+                                                            w.Mp, w.Kp, stream);
+            if (e != hipSuccess) return hip_status(e);
+            e = mg::launch_bf16_pack_interleaved(!tb, B, ldb, N, K, fast_operand(B, ldb), bhi, 2 * w.Kp, w.Np, w.Kp,
+                                                 stream);
+            if (e != hipSuccess) return hip_status(e);
+            g.A = reinterpret_cast<const float*>(ahi);
+            g.B = reinterpret_cast<const float*>(bhi);
+            g.lda = g.ldb = 2 * w.Kp;
+            return finish(mg::launch_gemm_bf16(terms, cfg, false, true, g, stream, true));
+        }
         hipError_t e = mg::launch_bf16_pack(ta, terms, A, lda, M, K, fast_operand(A, lda), ahi, alo, w.Kp,
                                             w.Mp, w.Kp, stream);
         if (e != hipSuccess) return hip_status(e);
@@ -587,7 +615,7 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     size_t left = (ws != nullptr && (reinterpret_cast<uintptr_t>(ws) & 255) == 0) ? workspace_bytes : 0;
     void* planes = nullptr;
-    if (is_16bit(path) && bf16_prepack_pays(path, M, N, K)) {
+    if (is_16bit(path) && uses_planes(path, cfg, M, N, K)) {
         const size_t need = align256(bf16_workspace(path, M, N, K).total);
         if (left >= need) {
             planes = ws;
@@ -614,9 +642,10 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int
     if (M <= 0 || N <= 0 || K <= 0 || !float_path(path) || beyond_int(M, N, K)) return 0;
     if (path == MG_PATH_FP8_T128) return K > kMaxFp8K ? 0 : fp8_workspace(M, N, K).total;
     size_t total = 0;
-    if (is_16bit(path) && bf16_prepack_pays(path, M, N, K))
+    const int cfg = pick_config(path, M, N, K);
+    if (is_16bit(path) && uses_planes(path, cfg, M, N, K))
         total += align256(bf16_workspace(path, M, N, K).total);
-    total += split_plan(path, pick_config(path, M, N, K), M, N, K).bytes;
+    total += split_plan(path, cfg, M, N, K).bytes;
     return total;
 }
 

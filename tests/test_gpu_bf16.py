@@ -194,17 +194,19 @@ def test_full_size_8192_sampled(gpu, path, dist):
     assert err <= TOL[path], err
 
 
-@pytest.mark.parametrize("path", ["bf16", "fp16"])
+@pytest.mark.parametrize("path", ["bf16", "fp16", "bf16x3"])
 @pytest.mark.parametrize("M,N,K,tA,tB,splits", [
     (512, 512, 32, "N", "N", -1), (777, 531, 203, "T", "N", -1), (600, 1030, 1500, "N", "T", 3),
     (513, 700, 129, "T", "T", -1), (1024, 768, 4096, "N", "N", 5)])
 def test_direct_copy_equals_staged_kernel_bitwise(gpu, path, M, N, K, tA, tB, splits):
-    """Configuration 6 copies the pre-packed planes' 64-deep panels straight
-    into LDS; its MFMA sequence over k is configuration 1's, so the two
-    results must agree bit for bit (ragged tiles, ragged K, split K ranges),
-    and both must meet the path's bound against the oracle."""
+    """Configuration 6 copies the pre-packed planes' panels straight into
+    LDS (bf16x3: one plane per operand with hi and lo interleaved per 32 k,
+    against configuration 1's conversion inside the GEMM); its MFMA sequence
+    over k is configuration 1's, so the two results must agree bit for bit
+    (ragged tiles, ragged K, split K ranges), and both must meet the path's
+    bound against the oracle."""
     nat = _native()
-    pid = {"bf16": 2, "fp16": 4}[path]
+    pid = {"bf16x3": 1, "bf16": 2, "fp16": 4}[path]
     outs = []
     for cfg in (1, 6):
         p = Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + N + K)

@@ -157,12 +157,15 @@ def test_split_plan_rules(native):
 
 
 def test_sixteen_bit_direct_copy_choice(native):
-    """BF16 and FP16 problems large enough for the pre-packed planes and for
-    256 x 256 tiles take configuration 6 (the same tiles, panels copied
-    straight into LDS); bf16x3, which converts in the kernel, and problems
-    too small to pre-pack keep configuration 1."""
-    for path in (2, 4):
+    """16-bit problems large enough for pre-packed planes and for 256 x 256
+    tiles take configuration 6 (the same tiles, panels copied straight into
+    LDS); problems too small to pre-pack, or beyond the planes' K limit,
+    keep configuration 1.  bf16x3 then asks for workspace for its
+    interleaved planes."""
+    for path in (1, 2, 4):
         assert native.mg_tuned_config(path, 8192, 8192, 8192) == 6
         assert native.mg_tuned_config(path, 256, 8192, 8192) == 1          # M < 512: no planes
-        assert native.mg_tuned_config(path, 8192, 8192, 2 ** 22 + 1) == 1  # beyond the planes' K limit
-    assert native.mg_tuned_config(1, 8192, 8192, 8192) == 1
+        assert native.mg_tuned_config(path, 8192, 8192, 2 ** 21 + 1) == 1  # beyond the planes' K limit
+    # interleaved hi/lo planes: 4 bytes per element of op(A) and op(B)^T
+    assert native.mg_gemm_workspace_size(1, "N", "N", 8192, 8192, 8192) == 4 * 2 * 8192 * 8192
+    assert native.mg_gemm_workspace_size(1, "N", "N", 256, 8192, 8192) > 0   # split-K partials only
