@@ -112,7 +112,13 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * 256-byte aligned, of mg_gemm_workspace_size() bytes.  It holds:
  *   - MG_PATH_FP8_T128: the packed FP8 operands (required: MG_ERR_WORKSPACE
  *     if missing or too small);
- *   - MG_PATH_BF16 with M, N >= 512: the operands rounded to bf16 once;
+ *   - MG_PATH_BF16 / MG_PATH_FP16 with M, N >= 512 and K <= 2^21: the
+ *     operands rounded to bf16 / binary16 once (padded to 256 rows and 128 k);
+ *   - MG_PATH_BF16X3 where it takes 256 x 256 tiles with M, N >= 512 and
+ *     K <= 2^21: the operands split once into hi and lo bf16 terms, stored
+ *     interleaved per 32 k (4 bytes per element);
+ *   on these 16-bit paths the large-tile kernel copies the pre-packed
+ *   panels straight into LDS;
  *   - every other path: the partial products of a split-K launch, used when
  *     the problem has fewer output tiles than the GPU has compute units and
  *     K >= 256 (the K loop is cut into ranges multiplied by separate
