@@ -32,111 +32,24 @@ void gemm_bf16_packed_kernel(GemmArgs args)
     bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS, true>(g, tm, tn, smem);
 }
 
-// Direct form on pre-packed single-term planes (direct_copy in tile_bytes.h):
-// each 64-deep K panel of op(A) and op(B)^T is 128 bytes per row, copied from
-// the planes straight into LDS while the previous panel is multiplied, with
-// no register staging and no LDS write instructions.  The two buffers are
-// separate arrays used in a fixed alternation, so the compiler can tell the
-// copy into one from the reads of the other.  The planes are zero-padded to
-// whole 256-row tiles and 128-deep K grains, so every copy is in bounds and
-// the padding adds zeros.
+// Direct form on pre-packed planes (direct_copy in tile_bytes.h): each K
+// panel is one 128-byte row per row of op(A) and op(B)^T, copied from the
+// planes straight into LDS while the previous panel is multiplied, with no
+// register staging and no LDS write instructions.  Single-term planes hold
+// 64 k per row; bf16x3's interleaved planes (launch_bf16_pack_interleaved)
+// hold 32 k of both terms, hi in global chunks 0-3 and lo in 4-7.  The two
+// buffers are separate arrays used in a fixed alternation, so the compiler
+// can tell the copy into one from the reads of the other.  The planes are
+// zero-padded to whole 256-row tiles and 128-deep K grains, so every copy is
+// in bounds and the padding adds zeros.  Each 16-deep step issues its
+// products in the order the staged kernel does (bf16x3: lo(A) hi(B),
+// hi(A) lo(B), hi(A) hi(B)), so the results are bit-identical to it.
 template <int BM, int BN, int WM, int WN, int TERMS>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void gemm_bf16_direct_kernel(GemmArgs args)
 {
-    static_assert(TERMS != 3, "the direct form multiplies single-term planes");
-    constexpr int BK = 64;                    // bf16 elements per panel row (128 bytes)
-    constexpr int STEPS = BK / 16;
-    constexpr int WAVES_N = BN / WN;
-    constexpr int NW = (BM / WM) * WAVES_N;
-    constexpr int V = WM / 32, H = WN / 32;
-
-    __shared__ __attribute__((aligned(1024))) uint8_t A0[BM * 128];
-    __shared__ __attribute__((aligned(1024))) uint8_t A1[BM * 128];
-    __shared__ __attribute__((aligned(1024))) uint8_t B0[BN * 128];
-    __shared__ __attribute__((aligned(1024))) uint8_t B1[BN * 128];
-
-    GemmArgs g = args;
-    split_k_view<false, true, true>(g);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
-    const int c = lane & 31, h = lane >> 5;
-
-    int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
-    const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-    const uint8_t* __restrict__ qa = reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda);
-    const uint8_t* __restrict__ qb = reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb);
-    const uint32_t lda32 = uint32_t(2 * g.lda), ldb32 = uint32_t(2 * g.ldb);
-
-    floatx16 acc[V][H];
-#pragma unroll
-    for (int i = 0; i < V; ++i)
-#pragma unroll
-        for (int j = 0; j < H; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    auto copy_panel = [&](uint8_t* LA, uint8_t* LB, int kp) {
-        direct_copy<BM, NW>(qa, lda32, uint32_t(kp) * 128u, LA, wave, lane);
-        direct_copy<BN, NW>(qb, ldb32, uint32_t(kp) * 128u, LB, wave, lane);
-    };
-    auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            // lane (c, h) supplies k 16s + 8h .. +7 of row c: global chunk 2s + h
-            bf16x8 a[V], b[H];
-#pragma unroll
-            for (int i = 0; i < V; ++i) a[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 2 * s + h));
-#pragma unroll
-            for (int j = 0; j < H; ++j) b[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 2 * s + h));
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<TERMS>(a[i], b[j], acc[i][j]);
-        }
-    };
-    // all copies landed in LDS, then every wave past the barrier
-    auto arrive = [&]() {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    };
-
-    const int nk = int((g.K + BK - 1) / BK);
-    if (nk > 0) {
-        copy_panel(A0, B0, 0);
-        arrive();
-    }
-    for (int kt = 0; kt < nk; kt += 2) {
-        // panel kt in buffer 0; panel kt+1 is copied into buffer 1 meanwhile
-        if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
-        panel(A0, B0);
-        arrive();
-        if (kt + 1 < nk) {
-            if (kt + 2 < nk) copy_panel(A0, B0, kt + 2);
-            panel(A1, B1);
-            arrive();
-        }
-    }
-
-    const float alpha = g.alpha, beta = g.beta;
-    store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
-                           [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
-}
-
-// bf16x3 direct form on the interleaved planes (launch_bf16_pack_interleaved):
-// a 32-deep panel of both terms is one 128-byte row (hi in global chunks
-// 0-3, lo in 4-7), copied straight into LDS as in the single-term kernel.
-// Per 16-deep step the three products are issued in the in-kernel
-// conversion's order (lo(A) hi(B), hi(A) lo(B), hi(A) hi(B)), so the result
-// is bit-identical to it.  Split K: workgroup row s takes the K range
-// [s k_chunk, ...), 4 bytes per k in these rows.
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
-void gemm_bf16x3_direct_kernel(GemmArgs args)
-{
-    constexpr int BK = 32;
+    constexpr int BK = TERMS == 3 ? 32 : 64;  // k per 128-byte panel row
+    constexpr int KBYTES = 128 / BK;          // bytes per k in a plane row
     constexpr int STEPS = BK / 16;
     constexpr int WAVES_N = BN / WN;
     constexpr int NW = (BM / WM) * WAVES_N;
@@ -150,9 +63,11 @@ void gemm_bf16x3_direct_kernel(GemmArgs args)
     GemmArgs g = args;
     int64_t kbyte0 = 0;
     if (gridDim.y > 1) {
+        // split K: workgroup row s multiplies the range [s k_chunk, ...) and
+        // stores its unscaled partial product (reduced afterwards)
         const int64_t k0 = int64_t(blockIdx.y) * g.k_chunk;
         g.K = min(g.k_chunk, g.K - k0);
-        kbyte0 = 4 * k0;
+        kbyte0 = KBYTES * k0;
         g.C = g.part + int64_t(blockIdx.y) * g.part_stride;
         g.ldc = g.ldp;
         g.alpha = 1.f;
@@ -184,36 +99,50 @@ void gemm_bf16x3_direct_kernel(GemmArgs args)
         direct_copy<BM, NW>(qa, lda32, uint32_t(kp) * 128u, LA, wave, lane);
         direct_copy<BN, NW>(qb, ldb32, uint32_t(kp) * 128u, LB, wave, lane);
     };
+    auto chunk = [&](const uint8_t* L, int row, int g) { return __builtin_bit_cast(bf16x8, direct_chunk(L, row, g)); };
     auto panel = [&](const uint8_t* LA, const uint8_t* LB) {
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
-            // lane (c, h) supplies k 16s + 8h .. +7 of row c: hi in global
-            // chunk 2s + h, lo in chunk 4 + 2s + h
-            bf16x8 ah[V], al[V], bh[H], bl[H];
+            // lane (c, h) supplies k 16s + 8h .. +7 of row c: global chunk
+            // 2s + h (bf16x3: hi there, lo in chunk 4 + 2s + h)
+            if constexpr (TERMS == 3) {
+                bf16x8 ah[V], al[V], bh[H], bl[H];
 #pragma unroll
-            for (int j = 0; j < H; ++j) {
-                bh[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 2 * s + h));
-                bl[j] = __builtin_bit_cast(bf16x8, direct_chunk(LB, wn0 + 32 * j + c, 4 + 2 * s + h));
+                for (int j = 0; j < H; ++j) {
+                    bh[j] = chunk(LB, wn0 + 32 * j + c, 2 * s + h);
+                    bl[j] = chunk(LB, wn0 + 32 * j + c, 4 + 2 * s + h);
+                }
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    ah[i] = chunk(LA, wm0 + 32 * i + c, 2 * s + h);
+                    al[i] = chunk(LA, wm0 + 32 * i + c, 4 + 2 * s + h);
+                }
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(al[i], bh[j], acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bh[j], acc[i][j]);
+            } else {
+                bf16x8 a[V], b[H];
+#pragma unroll
+                for (int i = 0; i < V; ++i) a[i] = chunk(LA, wm0 + 32 * i + c, 2 * s + h);
+#pragma unroll
+                for (int j = 0; j < H; ++j) b[j] = chunk(LB, wn0 + 32 * j + c, 2 * s + h);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j) acc[i][j] = mfma16<TERMS>(a[i], b[j], acc[i][j]);
             }
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-                ah[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 2 * s + h));
-                al[i] = __builtin_bit_cast(bf16x8, direct_chunk(LA, wm0 + 32 * i + c, 4 + 2 * s + h));
-            }
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(al[i], bh[j], acc[i][j]);
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bl[j], acc[i][j]);
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j) acc[i][j] = mfma16<3>(ah[i], bh[j], acc[i][j]);
         }
     };
+    // all copies landed in LDS, then every wave past the barrier
     auto arrive = [&]() {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -225,6 +154,7 @@ void gemm_bf16x3_direct_kernel(GemmArgs args)
         arrive();
     }
     for (int kt = 0; kt < nk; kt += 2) {
+        // panel kt in buffer 0; panel kt+1 is copied into buffer 1 meanwhile
         if (kt + 1 < nk) copy_panel(A1, B1, kt + 1);
         panel(A0, B0);
         arrive();
@@ -238,17 +168,6 @@ void gemm_bf16x3_direct_kernel(GemmArgs args)
     const float alpha = g.alpha, beta = g.beta;
     store_acc_blocks<V, H>(g.C, g.ldc, g.M, g.N, m0 + wm0, n0 + wn0, h, c, beta != 0.f, acc,
                            [&](float a, float c0) { return beta != 0.f ? __builtin_fmaf(alpha, a, beta * c0) : alpha * a; });
-}
-
-template <int BM, int BN, int WM, int WN>
-static hipError_t launch_bf16x3_direct(GemmArgs g, hipStream_t stream)
-{
-    constexpr int NT = (BM / WM) * (BN / WN) * 64;
-    g.tiles_m = int((g.M + BM - 1) / BM);
-    g.tiles_n = int((g.N + BN - 1) / BN);
-    const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
-    hipLaunchKernelGGL((gemm_bf16x3_direct_kernel<BM, BN, WM, WN>), grid, block, 0, stream, g);
-    return hipGetLastError();
 }
 
 template <int BM, int BN, int WM, int WN, int TERMS>
@@ -303,10 +222,7 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 4: return launch_bf16_cfg<64, 64, 32, 32, 32, TERMS>(ta, tb, g, stream, packed);
     case 5: return launch_bf16_cfg<128, 64, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
     case 6:
-        if (packed) {
-            if constexpr (TERMS == 3) return launch_bf16x3_direct<256, 256, 128, 64>(g, stream);
-            else return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
-        }
+        if (packed) return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
         return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
