@@ -209,10 +209,18 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         // panels copied straight into LDS (6), bit-identical to (1) and
         // faster (8192^3 end to end: BF16 1078-1080 against 975-997
         // TFLOP/s, FP16 1023-1030 against 941-948, bf16x3 430-433 against
-        // 354-360; bf16x3 wins or ties at every shape measured where (1)
-        // is chosen, 8192 x 4096 x 256 to 8192^3).  Without the planes'
-        // workspace configuration 6 runs as configuration 1.
-        if (ladder[i] == 1 && uses_planes(path, 6, M, N, K)) return 6;
+        // 354-360).  Without the planes' workspace configuration 6 runs as
+        // configuration 1.  bf16x3's pack reads and writes 4 bytes per
+        // element of both operands, which the faster GEMM repays only when
+        // each operand is re-read often enough: op(A) by the N / 256 column
+        // tiles, op(B) by the M / 256 row tiles, so 1/M + 1/N must be small.
+        // Measured end to end (NN): 4096^3 372 -> 398 TFLOP/s, 2048 x 8192 x
+        // 2048 335 -> 371, 8192 x 4096 x 256 238 -> 245; but 2048^3
+        // 231 -> 216 and 16384 x 1024 x 4096 365 -> 346, hence
+        // M N >= 1600 (M + N) for bf16x3.
+        if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
+            (path != MG_PATH_BF16X3 || M * N >= 1600 * (M + N)))
+            return 6;
         return ladder[i];
     }
     return ladder[2];
@@ -272,8 +280,7 @@ bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 // FP32 ones for no gain (about 347 against 370 TFLOP/s at 8192^3).
 bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K)
 {
-    if (path == MG_PATH_BF16X3)
-        return cfg == 6 && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+    if (path == MG_PATH_BF16X3) return cfg == 6 && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
     return bf16_prepack_pays(path, M, N, K);
 }
 
