@@ -115,7 +115,7 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  *   - MG_PATH_BF16 / MG_PATH_FP16 with M, N >= 512 and K <= 2^21: the
  *     operands rounded to bf16 / binary16 once (padded to 256 rows and 128 k);
  *   - MG_PATH_BF16X3 with configuration 6 (chosen for 256 x 256 tiles when
- *     M N >= 1600 (M + N)), M, N >= 512 and K <= 2^21: the operands split
+ *     M N >= 1250 (M + N)), M, N >= 512 and K <= 2^21: the operands split
  *     once into hi and lo bf16 terms, stored interleaved per 32 k (4 bytes
  *     per element);
  *   on these 16-bit paths the large-tile kernel copies the pre-packed

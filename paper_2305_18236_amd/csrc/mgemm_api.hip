@@ -214,12 +214,14 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         // element of both operands, which the faster GEMM repays only when
         // each operand is re-read often enough: op(A) by the N / 256 column
         // tiles, op(B) by the M / 256 row tiles, so 1/M + 1/N must be small.
-        // Measured end to end (NN): 4096^3 372 -> 398 TFLOP/s, 2048 x 8192 x
-        // 2048 335 -> 371, 8192 x 4096 x 256 238 -> 245; but 2048^3
-        // 231 -> 216 and 16384 x 1024 x 4096 365 -> 346, hence
-        // M N >= 1600 (M + N) for bf16x3.
+        // Measured end to end (NN, TFLOP/s): wins at 3072^3 198 -> 242,
+        // 4096 x 2048 x 8192 283 -> 347, 2048 x 8192 x 2048 342 -> 390,
+        // 4096^3 360 -> 409; losses at 2048^3 235 -> 224, 2048 x 2048 x 8192
+        // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
+        // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
+        // M N >= 1250 (M + N) for bf16x3.
         if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
-            (path != MG_PATH_BF16X3 || M * N >= 1600 * (M + N)))
+            (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
             return 6;
         return ladder[i];
     }

@@ -171,6 +171,10 @@ def test_sixteen_bit_direct_copy_choice(native):
     assert native.mg_tuned_config(1, 16384, 1024, 4096) == 1
     assert native.mg_tuned_config(1, 4096, 4096, 4096) == 6
     assert native.mg_tuned_config(1, 2048, 8192, 2048) == 6
+    assert native.mg_tuned_config(1, 3072, 3072, 3072) == 6
+    assert native.mg_tuned_config(1, 4096, 2048, 8192) == 6
+    assert native.mg_tuned_config(1, 1024, 8192, 4096) == 1
+    assert native.mg_tuned_config(1, 2048, 2048, 8192) == 1
     # interleaved hi/lo planes: 4 bytes per element of op(A) and op(B)^T
     assert native.mg_gemm_workspace_size(1, "N", "N", 8192, 8192, 8192) == 4 * 2 * 8192 * 8192
     assert native.mg_gemm_workspace_size(1, "N", "N", 256, 8192, 8192) > 0   # split-K partials only
