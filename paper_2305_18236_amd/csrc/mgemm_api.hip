@@ -75,6 +75,7 @@ bool fast_operand(const void* p, int64_t ld) { return aligned16(p) && ld % 4 == 
 bool beyond_int(int64_t a, int64_t b, int64_t c) { return a > INT_MAX || b > INT_MAX || c > INT_MAX; }
 
 int64_t tiles(int64_t M, int64_t N, int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); }
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 struct ConfigTable {
     const mg::SgemmConfig* cfgs;
@@ -161,30 +162,10 @@ int auto_splits(int64_t t, int64_t K)
 // with 64 x 64).
 bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K);
 
-int choose_config(int path, int64_t M, int64_t N, int64_t K)
+// The tile ladder (see choose_config): the largest tile whose tiles, times
+// the automatic split, give every compute unit a workgroup.
+int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
 {
-    const int64_t cus = device_cus();
-    if (path == MG_PATH_FP8_T128) {
-        // 256 x 256: panels copied straight into LDS (7): 2359-2418 TFLOP/s
-        // at 8192^3 against 2200-2378 for the interleaved pack (5) and 1970
-        // for the plain loop (4); 128 x 128: the interleaved pack (6) beats
-        // the direct copy (8), 1904-1954 vs 1764-1839
-        if (tiles(M, N, 256, 256) >= 256) return 7;
-        if (tiles(M, N, 128, 128) >= 128) return 6;
-        return 3;
-    }
-    if (path == MG_CONFIGS_I8) {
-        // 256 x 256: panels copied straight into LDS (5): 2255 TOP/s at
-        // 8192^3 against 2128-2190 for the interleaved pack (3) and 1870 for
-        // the plain loop (0); 128 x 128: the interleaved pack (4)
-        if (tiles(M, N, 256, 256) >= 256) return 5;
-        if (tiles(M, N, 128, 128) >= 128) return 4;
-        return 2;
-    }
-    // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the
-    // paper finds for small matrices (measured: 0.84x the packed time at 16^3,
-    // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
-    if (path == MG_PATH_FP32 && std::max({M, N, K}) <= 32) return 8;
     // tile ids by decreasing size: 256 x 256, 128 x 128, 64 x 64
     static const int kFp32Ladder[3] = {5, 0, 3};
     static const int kBf16Ladder[3] = {1, 2, 4};
@@ -228,13 +209,107 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     return ladder[2];
 }
 
+// ---- FP32 rounds of workgroups.  The ladder ignores how the workgroups
+// fall into rounds over the compute units: 3072^3 in 256 x 256 tiles and two
+// K ranges is 288 workgroups on 256 compute units, a second round nearly
+// empty (784 us, against 510 us for 64 x 64 tiles unsplit).  Where the
+// ladder's choice leaves its last round less than 80 % full, the plan below
+// compares the 256 x 256, 128 x 128 and 64 x 64 tiles with 1-8 K ranges by
+// a time model fitted to MI355X measurements (per compute unit: 0.55,
+// 0.494, 0.483 TFLOP/s and 32, 8, 2 us of fixed cost per round of 1, 2, 5
+// resident workgroups; partial products written and read at 4 TB/s, 5 us
+// for the reduction launch), and takes the best if it is 5 % faster.
+// Shapes whose rounds come out whole (every power-of-two shape from 2048^3
+// up) keep the ladder's choice.
+struct Fp32Plan {
+    int cfg;
+    int splits;   // requested K ranges; -1: the automatic split
+};
+
+int64_t effective_splits(int64_t K, int64_t s)
+{
+    if (s < 2 || K < 2 * kSplitGrain) return 1;
+    const int64_t chunk = round_up((K + s - 1) / s, kSplitGrain);
+    return (K + chunk - 1) / chunk;
+}
+
+double fp32_model_us(int cfg, int64_t M, int64_t N, int64_t K, int64_t s, int64_t cus)
+{
+    const int bm = cfg == 5 ? 256 : cfg == 0 ? 128 : 64;
+    const int64_t occ = cfg == 5 ? 1 : cfg == 0 ? 2 : 5;
+    const double rate = cfg == 5 ? 0.55 : cfg == 0 ? 0.494 : 0.483;   // TFLOP/s per compute unit
+    const double fixed = cfg == 5 ? 32.0 : cfg == 0 ? 8.0 : 2.0;      // us per round
+    const int64_t per_cu = (tiles(M, N, bm, bm) * s + cus - 1) / cus;
+    const double wg_us = 2.0 * bm * bm * double((K + s - 1) / s) / (rate * 1e6);
+    double t = double(per_cu) * wg_us + fixed * double((per_cu + occ - 1) / occ);
+    if (s > 1) t += 8.0 * double(s) * double(M) * double(N) / 4e6 + 5.0;
+    return t;
+}
+
+Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick)
+{
+    const Fp32Plan keep{pick, -1};
+    if ((pick != 5 && pick != 0) || M <= 0 || N <= 0 || K <= 0 || beyond_int(M, N, K)) return keep;
+    const int64_t cus = device_cus();
+    const int bm = pick == 5 ? 256 : 128;
+    const int64_t s0 = effective_splits(K, auto_splits(tiles(M, N, bm, bm), K));
+    const int64_t n = tiles(M, N, bm, bm) * s0;
+    const int64_t rounds = (n + cus - 1) / cus;
+    if (n * 10 >= rounds * cus * 8) return keep;   // last round at least 80 % full
+    Fp32Plan best = keep;
+    double best_t = 0.95 * fp32_model_us(pick, M, N, K, s0, cus);
+    static const int kCfgs[3] = {5, 0, 3};
+    static const int kSplits[6] = {1, 2, 3, 4, 6, 8};
+    for (int c : kCfgs) {
+        const int tb = c == 5 ? 256 : c == 0 ? 128 : 64;
+        for (int req : kSplits) {
+            const int64_t se = effective_splits(K, req);
+            if (req > 1 && (se < 2 || K / se < kMinRange)) continue;
+            if (tiles(M, N, tb, tb) * se < cus) continue;
+            const double t = fp32_model_us(c, M, N, K, se, cus);
+            if (t < best_t) {
+                best = Fp32Plan{c, req};
+                best_t = t;
+            }
+        }
+    }
+    return best;
+}
+
+int choose_config(int path, int64_t M, int64_t N, int64_t K)
+{
+    const int64_t cus = device_cus();
+    if (path == MG_PATH_FP8_T128) {
+        // 256 x 256: panels copied straight into LDS (7): 2359-2418 TFLOP/s
+        // at 8192^3 against 2200-2378 for the interleaved pack (5) and 1970
+        // for the plain loop (4); 128 x 128: the interleaved pack (6) beats
+        // the direct copy (8), 1904-1954 vs 1764-1839
+        if (tiles(M, N, 256, 256) >= 256) return 7;
+        if (tiles(M, N, 128, 128) >= 128) return 6;
+        return 3;
+    }
+    if (path == MG_CONFIGS_I8) {
+        // 256 x 256: panels copied straight into LDS (5): 2255 TOP/s at
+        // 8192^3 against 2128-2190 for the interleaved pack (3) and 1870 for
+        // the plain loop (0); 128 x 128: the interleaved pack (4)
+        if (tiles(M, N, 256, 256) >= 256) return 5;
+        if (tiles(M, N, 128, 128) >= 128) return 4;
+        return 2;
+    }
+    // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the
+    // paper finds for small matrices (measured: 0.84x the packed time at 16^3,
+    // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
+    if (path == MG_PATH_FP32 && std::max({M, N, K}) <= 32) return 8;
+    const int pick = ladder_choice(path, M, N, K, cus);
+    return path == MG_PATH_FP32 ? fp32_plan(M, N, K, pick).cfg : pick;
+}
+
 int pick_config(int path, int64_t M, int64_t N, int64_t K);
 
 // ---- FP8 packed layout: q is Rp x Kp bytes, scales (Rp/128) x (Kp/128) bytes.
 // The GEMM kernels address a 256-row panel of q with 32-bit byte offsets, so
 // K is limited to 2^23 (256 rows x 2^23 bytes = 2^31).
 constexpr int64_t kMaxFp8K = int64_t(1) << 23;
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 int64_t fp8_rows(int64_t R) { return round_up(R > 0 ? R : 1, 256); }
 int64_t fp8_kp(int64_t K) { return round_up(K > 0 ? K : 1, 128); }
 size_t fp8_q_bytes(int64_t R, int64_t K) { return size_t(fp8_rows(R)) * size_t(fp8_kp(K)); }
@@ -319,6 +394,11 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
     if (path == MG_PATH_FP8_T128 || path == MG_CONFIGS_I8 || M <= 0 || N <= 0 || K < 2 * kSplitGrain) return p;
     const mg::SgemmConfig& c = table_of(path).cfgs[cfg];
     int s = g_forced_splits[path].load();
+    if (s < 0 && path == MG_PATH_FP32) {
+        // the K ranges the round plan chose with this configuration
+        const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus()));
+        if (fp.cfg == cfg) s = fp.splits;
+    }
     if (s < 0) s = auto_splits(tiles(M, N, c.bm, c.bn), K);
     if (s < 2) return p;
     p.chunk = round_up((K + s - 1) / s, kSplitGrain);

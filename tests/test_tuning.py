@@ -178,3 +178,23 @@ def test_sixteen_bit_direct_copy_choice(native):
     # interleaved hi/lo planes: 4 bytes per element of op(A) and op(B)^T
     assert native.mg_gemm_workspace_size(1, "N", "N", 8192, 8192, 8192) == 4 * 2 * 8192 * 8192
     assert native.mg_gemm_workspace_size(1, "N", "N", 256, 8192, 8192) > 0   # split-K partials only
+
+
+def test_fp32_round_plan(native):
+    """Where the tile ladder's workgroups leave the last round on the compute
+    units mostly empty, the FP32 rule re-plans tile and K ranges (3072^3:
+    288 workgroups of 256 x 256 on 256 compute units before); shapes whose
+    rounds come out whole keep the ladder's choice."""
+    plan = lambda *s: (native.mg_tuned_config(0, *s), native.mg_split_count(0, *s))
+    assert plan(8192, 8192, 8192) == (5, 1)
+    assert plan(4096, 4096, 4096) == (5, 1)
+    assert plan(2048, 2048, 2048) == (5, 4)
+    assert plan(4096, 4096, 1024) == (5, 1)
+    assert plan(256, 8192, 8192) == (5, 8)
+    assert plan(8192, 8192, 256) == (4, 1)
+    assert plan(1024, 1024, 1024) == (3, 1)
+    assert plan(3072, 3072, 3072) == (3, 1)
+    assert plan(6144, 6144, 6144) == (0, 1)
+    assert plan(1536, 1536, 4096) == (3, 4)
+    # the workspace query follows the plan's K ranges
+    assert native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 4096) == 4 * 1536 * 1536 * 4
