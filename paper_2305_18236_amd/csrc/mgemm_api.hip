@@ -142,6 +142,20 @@ constexpr int kMaxSplits = 16;
 
 // Split factor the automatic rule gives `t` output tiles: enough K ranges for
 // one workgroup per compute unit, each at least kMinRange deep.
+// The 16-bit paths' split rule.  Their GEMMs run two to eight times faster
+// than FP32, so the partial products of a split cost relatively more: a
+// tile count that keeps half the compute units busy runs unsplit, and a
+// split is cut so that its workgroups fit one round (floor, not ceiling).
+// Measured (us, automatic rule before -> after): BF16 3072^3 127.7 -> 97.1,
+// 3072 x 3072 x 1024 75.3 -> 46.4; bf16x3 3072^3 238.8 -> 218.6, 3072 x
+// 3072 x 1024 111.4 -> 78.4.
+int splits_16bit(int64_t t, int64_t K, int64_t cus)
+{
+    if (t <= 0 || 2 * t >= cus) return 1;
+    const int64_t s = std::min<int64_t>({cus / t, K / kMinRange, kMaxSplits});
+    return s < 2 ? 1 : int(s);
+}
+
 int auto_splits(int64_t t, int64_t K)
 {
     const int64_t cus = device_cus();
@@ -175,6 +189,30 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
     for (int i = 0; i < 3; ++i) {
         const mg::SgemmConfig& c = t.cfgs[ladder[i]];
         const int64_t n = tiles(M, N, c.bm, c.bn);
+        if (path != MG_PATH_FP32) {
+            // 16-bit paths: this tile if its workgroups keep half the
+            // compute units busy (see splits_16bit).  On pre-packed planes:
+            // the same 256 x 256 tiles with
+            // panels copied straight into LDS (6), bit-identical to (1) and
+            // faster (8192^3 end to end: BF16 1078-1080 against 975-997
+            // TFLOP/s, FP16 1023-1030 against 941-948, bf16x3 430-433 against
+            // 354-360).  Without the planes' workspace configuration 6 runs as
+            // configuration 1.  bf16x3's pack reads and writes 4 bytes per
+            // element of both operands, which the faster GEMM repays only when
+            // each operand is re-read often enough: op(A) by the N / 256 column
+            // tiles, op(B) by the M / 256 row tiles, so 1/M + 1/N must be small.
+            // Measured end to end (NN, TFLOP/s): wins at 3072^3 198 -> 242,
+            // 4096 x 2048 x 8192 283 -> 347, 2048 x 8192 x 2048 342 -> 390,
+            // 4096^3 360 -> 409; losses at 2048^3 235 -> 224, 2048 x 2048 x 8192
+            // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
+            // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
+            // M N >= 1250 (M + N) for bf16x3.
+            if (n * splits_16bit(n, K, cus) * 2 < cus) continue;
+            if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
+                (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
+                return 6;
+            return ladder[i];
+        }
         const int s = auto_splits(n, K);
         if (n * s < cus) continue;
         // FP32: when this tile needs K ranges as short as kMinRange to fill
@@ -182,28 +220,10 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
         // wins (1024^3, beta 0.5: 64 x 64 unsplit 31.6 us, 128 x 128 in four
         // 256-deep ranges plus the reduction 37.6 us).  bf16x3 keeps the split
         // there (25.0 us against 32.0 us).
-        if (path == MG_PATH_FP32 && s > 1 && K / s <= kMinRange && i + 1 < 3) {
+        if (s > 1 && K / s <= kMinRange && i + 1 < 3) {
             const mg::SgemmConfig& d = t.cfgs[ladder[i + 1]];
             if (tiles(M, N, d.bm, d.bn) >= cus) return ladder[i + 1];
         }
-        // 16-bit paths on pre-packed planes: the same 256 x 256 tiles with
-        // panels copied straight into LDS (6), bit-identical to (1) and
-        // faster (8192^3 end to end: BF16 1078-1080 against 975-997
-        // TFLOP/s, FP16 1023-1030 against 941-948, bf16x3 430-433 against
-        // 354-360).  Without the planes' workspace configuration 6 runs as
-        // configuration 1.  bf16x3's pack reads and writes 4 bytes per
-        // element of both operands, which the faster GEMM repays only when
-        // each operand is re-read often enough: op(A) by the N / 256 column
-        // tiles, op(B) by the M / 256 row tiles, so 1/M + 1/N must be small.
-        // Measured end to end (NN, TFLOP/s): wins at 3072^3 198 -> 242,
-        // 4096 x 2048 x 8192 283 -> 347, 2048 x 8192 x 2048 342 -> 390,
-        // 4096^3 360 -> 409; losses at 2048^3 235 -> 224, 2048 x 2048 x 8192
-        // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
-        // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
-        // M N >= 1250 (M + N) for bf16x3.
-        if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
-            (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
-            return 6;
         return ladder[i];
     }
     return ladder[2];
@@ -399,7 +419,8 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus()));
         if (fp.cfg == cfg) s = fp.splits;
     }
-    if (s < 0) s = auto_splits(tiles(M, N, c.bm, c.bn), K);
+    if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)
+                                        : splits_16bit(tiles(M, N, c.bm, c.bn), K, device_cus());
     if (s < 2) return p;
     p.chunk = round_up((K + s - 1) / s, kSplitGrain);
     p.splits = int((K + p.chunk - 1) / p.chunk);
