@@ -142,16 +142,17 @@ constexpr int kMaxSplits = 16;
 
 // Split factor the automatic rule gives `t` output tiles: enough K ranges for
 // one workgroup per compute unit, each at least kMinRange deep.
-// The 16-bit paths' split rule.  Their GEMMs run two to eight times faster
-// than FP32, so the partial products of a split cost relatively more: a
-// tile count that keeps half the compute units busy runs unsplit, and a
-// split is cut so that its workgroups fit one round (floor, not ceiling).
-// Measured (us, automatic rule before -> after): BF16 3072^3 127.7 -> 97.1,
-// 3072 x 3072 x 1024 75.3 -> 46.4; bf16x3 3072^3 238.8 -> 218.6, 3072 x
-// 3072 x 1024 111.4 -> 78.4.
+// The 16-bit paths' split rule: as many K ranges as fit one round of
+// workgroups (rounded down, where the FP32 rule rounds up).  Their GEMMs run
+// two to eight times faster than FP32, so a second, nearly empty round of
+// split workgroups costs more than the idle compute units of an unsplit
+// one: 144 tiles (3072^3) run unsplit, 128 tiles (4096 x 2048 x 8192) in two
+// ranges.  Measured (us, rounded up -> down): BF16 3072^3 131.1 -> 101.8,
+// 3072 x 3072 x 1024 75.6 -> 47.8; bf16x3 3072^3 249.3 -> 208.8, 1536 x
+// 1536 x 4096 125.6 -> 86.2.
 int splits_16bit(int64_t t, int64_t K, int64_t cus)
 {
-    if (t <= 0 || 2 * t >= cus) return 1;
+    if (t <= 0 || t >= cus) return 1;
     const int64_t s = std::min<int64_t>({cus / t, K / kMinRange, kMaxSplits});
     return s < 2 ? 1 : int(s);
 }

@@ -201,8 +201,8 @@ def test_fp32_round_plan(native):
 
 
 def test_sixteen_bit_split_rule(native):
-    """16-bit paths split K only when the tiles keep fewer than half the
-    compute units busy, and then into as many ranges as fit one round."""
+    """16-bit paths split K into as many ranges as fit one round of
+    workgroups (rounded down)."""
     for path in (1, 2, 4):
         assert native.mg_split_count(path, 3072, 3072, 3072) == 1     # 144 tiles of 256 x 256
         assert native.mg_split_count(path, 3072, 3072, 1024) == 1
@@ -210,3 +210,4 @@ def test_sixteen_bit_split_rule(native):
         assert native.mg_split_count(path, 1536, 1536, 4096) == 7     # 36 tiles: 252 workgroups
         assert native.mg_split_count(path, 2048, 2048, 2048) == 4     # 64 tiles: 256 workgroups
         assert native.mg_split_count(path, 8192, 8192, 8192) == 1
+        assert native.mg_split_count(path, 4096, 2048, 8192) == 2     # 128 tiles: 256 workgroups
