@@ -304,8 +304,11 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
         // 256 x 256: panels copied straight into LDS (7): 2359-2418 TFLOP/s
         // at 8192^3 against 2200-2378 for the interleaved pack (5) and 1970
         // for the plain loop (4); 128 x 128: the interleaved pack (6) beats
-        // the direct copy (8), 1904-1954 vs 1764-1839
-        if (tiles(M, N, 256, 256) >= 256) return 7;
+        // the direct copy (8), 1904-1954 vs 1764-1839.  The big tile wins as
+        // soon as its tiles keep more than half the compute units busy
+        // (3072^3, 144 tiles: 45.7 us against 48.8 us; 2560^3, 100 tiles:
+        // 128 x 128 is best, 28.5 us).
+        if (tiles(M, N, 256, 256) * 2 > cus) return 7;
         if (tiles(M, N, 128, 128) >= 128) return 6;
         return 3;
     }

@@ -211,3 +211,11 @@ def test_sixteen_bit_split_rule(native):
         assert native.mg_split_count(path, 2048, 2048, 2048) == 4     # 64 tiles: 256 workgroups
         assert native.mg_split_count(path, 8192, 8192, 8192) == 1
         assert native.mg_split_count(path, 4096, 2048, 8192) == 2     # 128 tiles: 256 workgroups
+
+
+def test_fp8_big_tile_threshold(native):
+    """FP8 takes the 256 x 256 direct-copy tile once its tiles keep more than
+    half the compute units busy (FP8 never splits K)."""
+    assert native.mg_tuned_config(3, 3072, 3072, 3072) == 7     # 144 tiles
+    assert native.mg_tuned_config(3, 2560, 2560, 2560) == 6     # 100 tiles
+    assert native.mg_tuned_config(3, 8192, 8192, 8192) == 7
