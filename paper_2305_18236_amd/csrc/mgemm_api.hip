@@ -315,8 +315,11 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     if (path == MG_CONFIGS_I8) {
         // 256 x 256: panels copied straight into LDS (5): 2255 TOP/s at
         // 8192^3 against 2128-2190 for the interleaved pack (3) and 1870 for
-        // the plain loop (0); 128 x 128: the interleaved pack (4)
-        if (tiles(M, N, 256, 256) >= 256) return 5;
+        // the plain loop (0); 128 x 128: the interleaved pack (4).  As for
+        // FP8, the big tile from more than half the compute units' worth of
+        // tiles on (3072^3, 144 tiles: 47.5 us against 54.1 us; 4096 x 2048 x
+        // 8192, 128 tiles: 81.2 us for 128 x 128 against 100.6 us)
+        if (tiles(M, N, 256, 256) * 2 > cus) return 5;
         if (tiles(M, N, 128, 128) >= 128) return 4;
         return 2;
     }

@@ -219,3 +219,5 @@ def test_fp8_big_tile_threshold(native):
     assert native.mg_tuned_config(3, 3072, 3072, 3072) == 7     # 144 tiles
     assert native.mg_tuned_config(3, 2560, 2560, 2560) == 6     # 100 tiles
     assert native.mg_tuned_config(3, 8192, 8192, 8192) == 7
+    assert native.mg_tuned_config(5, 3072, 3072, 3072) == 5     # INT8, 144 tiles
+    assert native.mg_tuned_config(5, 4096, 2048, 8192) == 4     # INT8, 128 tiles
