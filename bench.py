@@ -500,7 +500,10 @@ def bench_fp8(args, torch, si, native, dev):
 
 
 SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
-                (8192, 8192, 256), (256, 8192, 8192), (16384, 1024, 4096)]
+                (8192, 8192, 256), (256, 8192, 8192), (16384, 1024, 4096),
+                # shapes whose workgroups do not fall into whole rounds over the
+                # compute units (the FP32 round plan and the 16-bit split rule)
+                (1536, 1536, 1536), (3072, 3072, 3072), (6144, 6144, 6144), (3072, 3072, 1024)]
 
 
 def bench_sweep(args, torch, si, native, dev):
