@@ -238,8 +238,9 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
 // compares the 256 x 256, 128 x 128 and 64 x 64 tiles with 1-8 K ranges by
 // a time model fitted to MI355X measurements (per compute unit: 0.55,
 // 0.494, 0.483 TFLOP/s and 32, 8, 2 us of fixed cost per round of 1, 2, 5
-// resident workgroups; partial products written and read at 4 TB/s, 5 us
-// for the reduction launch), and takes the best if it is 5 % faster.
+// resident workgroups, half that for split workgroups, which do not read C;
+// the reduction streams the partials and C at 5 TB/s, plus 5 us), and takes
+// the best if it is 5 % faster.
 // Shapes whose rounds come out whole (every power-of-two shape from 2048^3
 // up) keep the ladder's choice.
 struct Fp32Plan {
@@ -262,8 +263,10 @@ double fp32_model_us(int cfg, int64_t M, int64_t N, int64_t K, int64_t s, int64_
     const double fixed = cfg == 5 ? 32.0 : cfg == 0 ? 8.0 : 2.0;      // us per round
     const int64_t per_cu = (tiles(M, N, bm, bm) * s + cus - 1) / cus;
     const double wg_us = 2.0 * bm * bm * double((K + s - 1) / s) / (rate * 1e6);
-    double t = double(per_cu) * wg_us + fixed * double((per_cu + occ - 1) / occ);
-    if (s > 1) t += 8.0 * double(s) * double(M) * double(N) / 4e6 + 5.0;
+    // a split's workgroups store partial products without reading C (half
+    // the fixed cost); the reduction then streams s partials and C at 5 TB/s
+    double t = double(per_cu) * wg_us + (s > 1 ? 0.5 : 1.0) * fixed * double((per_cu + occ - 1) / occ);
+    if (s > 1) t += 4.0 * double(s + 1) * double(M) * double(N) / 5e6 + 5.0;
     return t;
 }
 

@@ -194,7 +194,8 @@ def test_fp32_round_plan(native):
     assert plan(8192, 8192, 256) == (4, 1)
     assert plan(1024, 1024, 1024) == (3, 1)
     assert plan(3072, 3072, 3072) == (3, 1)
-    assert plan(6144, 6144, 6144) == (0, 1)
+    assert plan(6144, 6144, 6144) == (5, 4)
+    assert plan(1536, 1536, 1536) == (3, 4)
     assert plan(1536, 1536, 4096) == (3, 4)
     # the workspace query follows the plan's K ranges
     assert native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 4096) == 4 * 1536 * 1536 * 4
