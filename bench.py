@@ -554,7 +554,7 @@ TILING_SIZES = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
 
 
 def bench_tiling(args, torch, si, native, dev):
-    """The packing ablation of the paper's Section 4.1.2 on the FP32 path:
+    """The packing ablation of the paper's Section 4.1.3 on the FP32 path:
     square SGEMMs C = A B (NN, alpha 1, beta 0) over the paper's sizes, each
     timed with every tile configuration; "Tiling" is the best configuration
     that loads operands straight into registers, "Tiling+Packing" the best one
@@ -615,7 +615,7 @@ VALU_FP32_PEAK = 256 * 256 * 2.4e9 / 1e12
 
 
 def bench_engine(args, torch, si, native, dev):
-    """The paper's generic-vs-MMA lowering comparison (Section 4.3) on the GPU:
+    """The paper's generic-vs-MMA lowering comparison (Section 4.4) on the GPU:
     the same packed macro level with the vector-ALU FMA micro-kernel and with
     the MFMA micro-kernel, square FP32 SGEMMs (NN, alpha 1.5, beta 0.5).  MFMA
     runs the automatic configuration; VALU the best of its configurations."""

@@ -124,8 +124,11 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  *     the problem has fewer output tiles than the GPU has compute units and
  *     K >= 256 (the K loop is cut into ranges multiplied by separate
  *     workgroups, then summed in a fixed order, so results stay deterministic).
- * On the non-FP8 paths the workspace is optional: with NULL or too few bytes
- * the GEMM runs without the optimisation that needed it.  Returns
+ * On the non-FP8 paths the workspace is optional: with NULL or fewer bytes
+ * than mg_gemm_workspace_size() the GEMM is planned as if no K split were
+ * possible (the tile shape chosen for an unsplit K loop; mg_sgemm always runs
+ * this way), pre-packing the 16-bit operands if the planes still fit
+ * (mg_gemm_plan tells which plan a given workspace gets).  Returns
  * MG_ERR_UNSUPPORTED for an unknown path.  Concurrent calls must not share a
  * workspace.
  */
@@ -138,6 +141,22 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
  * state (forced configuration, tuning table, forced split; 0 when none). */
 size_t mg_gemm_workspace_size(int path, char transA, char transB,
                               int64_t M, int64_t N, int64_t K);
+
+/*
+ * The plan mg_gemm would run for this problem, given `workspace_bytes` of
+ * 256-byte-aligned workspace, with the current selection state (the blocking
+ * decision of Section 3.1, Eq. 1-7, made per shape): out3[0] = the
+ * configuration id (mg_config_info), out3[1] = the number of K ranges (1: no
+ * split), out3[2] = 1 if the operands are pre-packed into the workspace.
+ * With the full mg_gemm_workspace_size() the plan is the best one; with less
+ * the GEMM is planned as if no K split were possible (the tile chosen for an
+ * unsplit K loop), using the pre-packed 16-bit planes if they still fit.
+ * Host-only: no device call.  Errors: MG_ERR_UNSUPPORTED unknown path,
+ * -2 M < 0, -3 N < 0, -4 K < 0, -6 out3 NULL, MG_ERR_TOO_LARGE as mg_gemm;
+ * MG_PATH_FP8_T128 with too little workspace fills out3 and returns
+ * MG_ERR_WORKSPACE, as mg_gemm would.
+ */
+int mg_gemm_plan(int path, int64_t M, int64_t N, int64_t K, size_t workspace_bytes, int *out3);
 
 /*
  * SYR2K, the paper's extension of the macro level to another BLAS kernel
@@ -207,7 +226,7 @@ int mg_config_info(int path, int index, int *out6);
 /*
  * 1 if configuration `index` of `path` packs its operand panels into LDS
  * before the micro-kernel reads them (the paper's Tiling+Packing strategy,
- * Section 4.1.2), 0 if its lanes load operands straight from global memory
+ * Section 4.1.3), 0 if its lanes load operands straight from global memory
  * into registers (the Tiling strategy: tiled loops, no packing), or
  * MG_ERR_UNSUPPORTED for an unknown (path, index).
  */

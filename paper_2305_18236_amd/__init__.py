@@ -35,11 +35,26 @@ def operand_layout(X):
         raise ValueError("operands must be 2-D")
     r, c = X.shape
     s0, s1 = X.stride()
-    if s1 == 1 or c <= 1:
-        return "N", max(s0, c, 1)
-    if s0 == 1 or r <= 1:
-        return "T", max(s1, r, 1)
+    # A stride only matters along a dimension longer than 1; where it matters
+    # it is taken as it is (never raised), so a broadcast view (stride 0) or
+    # rows that overlap are refused instead of being read out of bounds.
+    if (s1 == 1 or c <= 1) and (r <= 1 or s0 >= max(c, 1)):
+        return "N", s0 if r > 1 else max(c, 1)
+    if (s0 == 1 or r <= 1) and (c <= 1 or s1 >= max(r, 1)):
+        return "T", s1 if c > 1 else max(r, 1)
     raise ValueError(f"operand strides {X.stride()} are neither row- nor column-major")
+
+
+def output_ld(C) -> int:
+    """Row stride of an output C (M x N) with unit column stride; rows that
+    overlap (a broadcast or otherwise aliased view) are refused, since the
+    kernels would write past the tensor's storage."""
+    M, N = C.shape
+    if C.stride(1) != 1 and N > 1:
+        raise ValueError("C must have unit column stride")
+    if M > 1 and C.stride(0) < max(N, 1):
+        raise ValueError(f"C strides {C.stride()} make rows overlap")
+    return C.stride(0) if M > 1 else max(N, 1)
 
 
 def _stream_ptr(device):
@@ -69,14 +84,14 @@ def gemm(A, B, C=None, *, alpha: float = 1.0, beta: float = 0.0, path="fp32", wo
         C = torch.empty((M, N), dtype=torch.float32, device=A.device)
     if C.dtype != torch.float32 or tuple(C.shape) != (M, N) or not C.is_cuda:
         raise ValueError("C must be a float32 M x N GPU tensor")
-    if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
-        raise ValueError("C must have unit column stride")
+    if C.dim() != 2:
+        raise ValueError("C must be 2-D")
+    ldc = output_ld(C)
     for X in (A, B):
         if X.numel() and C.numel() and X.data_ptr() == C.data_ptr():
             raise ValueError("C must not alias A or B")
     tA, lda = operand_layout(A)
     tB, ldb = operand_layout(B)
-    ldc = max(C.stride(0), N, 1)
     pid = _path_id(path)
     need = _native.mg_gemm_workspace_size(pid, tA, tB, M, N, K)
     ws_ptr, ws_bytes = None, 0
@@ -109,8 +124,9 @@ def gemm_i8(A, B, C=None, *, alpha: int = 1, beta: int = 0, workspace=None):
         C = torch.empty((M, N), dtype=torch.int32, device=A.device)
     if C.dtype != torch.int32 or tuple(C.shape) != (M, N) or not C.is_cuda:
         raise ValueError("C must be an int32 M x N GPU tensor")
-    if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
-        raise ValueError("C must have unit column stride")
+    if C.dim() != 2:
+        raise ValueError("C must be 2-D")
+    ldc = output_ld(C)
     tA, lda = operand_layout(A)
     tB, ldb = operand_layout(B)
     need = _native.mg_gemm_i8_workspace_size(M, N, K)
@@ -120,7 +136,7 @@ def gemm_i8(A, B, C=None, *, alpha: int = 1, beta: int = 0, workspace=None):
             workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     st = _native.mg_gemm_i8(tA, tB, M, N, K, int(alpha), A.data_ptr(), lda, B.data_ptr(), ldb, int(beta),
-                            C.data_ptr(), max(C.stride(0), N, 1), ws_ptr, ws_bytes, _stream_ptr(A.device))
+                            C.data_ptr(), ldc, ws_ptr, ws_bytes, _stream_ptr(A.device))
     check(st, "mg_gemm_i8")
     return C
 
@@ -143,12 +159,14 @@ def gemm_batched(problems, *, path="fp32", workspace=None):
         K2, N = B.shape
         if K2 != K or tuple(C.shape) != (M, N):
             raise ValueError(f"problem {i}: shapes {tuple(A.shape)} x {tuple(B.shape)} -> {tuple(C.shape)}")
-        if C.dim() != 2 or (C.stride(1) != 1 and N > 1):
-            raise ValueError(f"problem {i}: C must have unit column stride")
+        try:
+            ldc = output_ld(C)
+        except ValueError as e:
+            raise ValueError(f"problem {i}: {e}") from None
         tA, lda = operand_layout(A)
         tB, ldb = operand_layout(B)
         arr[i] = _native.mg_problem(tA.encode(), tB.encode(), M, N, K, float(alpha), float(beta),
-                                    A.data_ptr(), lda, B.data_ptr(), ldb, C.data_ptr(), max(C.stride(0), N, 1))
+                                    A.data_ptr(), lda, B.data_ptr(), ldb, C.data_ptr(), ldc)
         dev = A.device
     if not problems:
         return

@@ -71,6 +71,8 @@ def lib():
     L.mg_force_splits.restype = ci
     L.mg_split_count.argtypes = [ci, i64, i64, i64]
     L.mg_split_count.restype = ci
+    L.mg_gemm_plan.argtypes = [ci, i64, i64, i64, ctypes.c_size_t, ctypes.POINTER(ci)]
+    L.mg_gemm_plan.restype = ci
     L.mg_bf16_split.argtypes = [vp, i64, vp, vp, vp]
     L.mg_bf16_split.restype = ci
     sz = ctypes.c_size_t
@@ -284,3 +286,10 @@ def mg_force_splits(path, splits) -> int:
 
 def mg_split_count(path, M, N, K) -> int:
     return int(lib().mg_split_count(int(path), M, N, K))
+
+
+def mg_gemm_plan(path, M, N, K, workspace_bytes):
+    """(status, config, splits, prepacked) of the plan mg_gemm would run."""
+    out = (ctypes.c_int * 3)()
+    st = int(lib().mg_gemm_plan(int(path), M, N, K, int(workspace_bytes), out))
+    return st, int(out[0]), int(out[1]), int(out[2])

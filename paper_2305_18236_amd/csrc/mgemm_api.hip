@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -179,7 +180,7 @@ bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K);
 
 // The tile ladder (see choose_config): the largest tile whose tiles, times
 // the automatic split, give every compute unit a workgroup.
-int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
+int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool split_ok)
 {
     // tile ids by decreasing size: 256 x 256, 128 x 128, 64 x 64
     static const int kFp32Ladder[3] = {5, 0, 3};
@@ -208,13 +209,13 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus)
             // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
             // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
             // M N >= 1250 (M + N) for bf16x3.
-            if (n * splits_16bit(n, K, cus) * 2 < cus) continue;
+            if (n * (split_ok ? splits_16bit(n, K, cus) : 1) * 2 < cus) continue;
             if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
                 (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
                 return 6;
             return ladder[i];
         }
-        const int s = auto_splits(n, K);
+        const int s = split_ok ? auto_splits(n, K) : 1;
         if (n * s < cus) continue;
         // FP32: when this tile needs K ranges as short as kMinRange to fill
         // the GPU and the next smaller tile fills it unsplit, the smaller one
@@ -270,13 +271,13 @@ double fp32_model_us(int cfg, int64_t M, int64_t N, int64_t K, int64_t s, int64_
     return t;
 }
 
-Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick)
+Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 {
     const Fp32Plan keep{pick, -1};
     if ((pick != 5 && pick != 0) || M <= 0 || N <= 0 || K <= 0 || beyond_int(M, N, K)) return keep;
     const int64_t cus = device_cus();
     const int bm = pick == 5 ? 256 : 128;
-    const int64_t s0 = effective_splits(K, auto_splits(tiles(M, N, bm, bm), K));
+    const int64_t s0 = split_ok ? effective_splits(K, auto_splits(tiles(M, N, bm, bm), K)) : 1;
     const int64_t n = tiles(M, N, bm, bm) * s0;
     const int64_t rounds = (n + cus - 1) / cus;
     if (n * 10 >= rounds * cus * 8) return keep;   // last round at least 80 % full
@@ -287,6 +288,7 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick)
     for (int c : kCfgs) {
         const int tb = c == 5 ? 256 : c == 0 ? 128 : 64;
         for (int req : kSplits) {
+            if (req > 1 && !split_ok) break;
             const int64_t se = effective_splits(K, req);
             if (req > 1 && (se < 2 || K / se < kMinRange)) continue;
             if (tiles(M, N, tb, tb) * se < cus) continue;
@@ -300,7 +302,7 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick)
     return best;
 }
 
-int choose_config(int path, int64_t M, int64_t N, int64_t K)
+int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
 {
     const int64_t cus = device_cus();
     if (path == MG_PATH_FP8_T128) {
@@ -330,11 +332,11 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K)
     // paper finds for small matrices (measured: 0.84x the packed time at 16^3,
     // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
     if (path == MG_PATH_FP32 && std::max({M, N, K}) <= 32) return 8;
-    const int pick = ladder_choice(path, M, N, K, cus);
-    return path == MG_PATH_FP32 ? fp32_plan(M, N, K, pick).cfg : pick;
+    const int pick = ladder_choice(path, M, N, K, cus, split_ok);
+    return path == MG_PATH_FP32 ? fp32_plan(M, N, K, pick, split_ok).cfg : pick;
 }
 
-int pick_config(int path, int64_t M, int64_t N, int64_t K);
+int pick_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok = true);
 
 // ---- FP8 packed layout: q is Rp x Kp bytes, scales (Rp/128) x (Kp/128) bytes.
 // The GEMM kernels address a 256-row panel of q with 32-bit byte offsets, so
@@ -418,15 +420,16 @@ struct SplitPlan {
     size_t bytes;
 };
 
-SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K)
+SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool split_ok = true)
 {
     SplitPlan p{1, 0, 0, 0, 0};
-    if (path == MG_PATH_FP8_T128 || path == MG_CONFIGS_I8 || M <= 0 || N <= 0 || K < 2 * kSplitGrain) return p;
+    if (!split_ok || path == MG_PATH_FP8_T128 || path == MG_CONFIGS_I8 || M <= 0 || N <= 0 || K < 2 * kSplitGrain)
+        return p;
     const mg::SgemmConfig& c = table_of(path).cfgs[cfg];
     int s = g_forced_splits[path].load();
     if (s < 0 && path == MG_PATH_FP32) {
         // the K ranges the round plan chose with this configuration
-        const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus()));
+        const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
         if (fp.cfg == cfg) s = fp.splits;
     }
     if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)
@@ -464,8 +467,6 @@ int run_i8_pack(bool trans, int64_t R, int64_t K, const int8_t* X, int64_t ldx, 
     return hip_status(mg::launch_i8_pack(trans, X, ldx, R, K, vec, q, fp8_kp(K), fp8_rows(R), fp8_kp(K), stream));
 }
 
-int pick_config(int path, int64_t M, int64_t N, int64_t K);
-
 int run_i8_packed(int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t* qA, const int8_t* qB, int32_t beta,
                   int32_t* C, int64_t ldc, hipStream_t stream)
 {
@@ -501,14 +502,45 @@ int run_fp8_pack(bool trans, int64_t R, int64_t K, const float* X, int64_t ldx, 
     return hip_status(mg::launch_fp8_pack(trans, X, ldx, R, K, vec, q, Kp, sc, Kp / 128, Rp, Kp, stream));
 }
 
-// forced > tuned > default rule
-int pick_config(int path, int64_t M, int64_t N, int64_t K)
+// forced > tuned > default rule.  split_ok: whether a K split may be planned
+// (false when the caller's workspace cannot hold the partial products).
+int pick_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
 {
     int cfg = g_forced[path].load();
     if (cfg >= 0) return cfg;
     cfg = table_lookup(path, M, N, K);
     if (config_valid(path, cfg)) return cfg;
-    return choose_config(path, M, N, K);
+    return choose_config(path, M, N, K, split_ok);
+}
+
+// What mg_gemm runs on a non-FP8 path for a workspace of `avail` usable
+// bytes: the best plan when the workspace holds everything it needs (the
+// pre-packed 16-bit planes and the split-K partials); otherwise the plan
+// made as if no split were possible (a configuration chosen for an unsplit
+// K loop), with the planes when they still fit.
+struct GemmPlan {
+    int cfg;
+    SplitPlan split;
+    size_t planes;   // bytes of pre-packed planes at the start of the workspace (0: none)
+};
+
+GemmPlan plan_gemm(int path, int64_t M, int64_t N, int64_t K, size_t avail)
+{
+    auto planes_of = [&](int cfg) -> size_t {
+        return is_16bit(path) && uses_planes(path, cfg, M, N, K) ? align256(bf16_workspace(path, M, N, K).total) : 0;
+    };
+    GemmPlan p{pick_config(path, M, N, K, true), {}, 0};
+    p.split = split_plan(path, p.cfg, M, N, K, true);
+    const size_t planes = planes_of(p.cfg);
+    if (avail >= planes + p.split.bytes) {
+        p.planes = planes;
+        return p;
+    }
+    p.cfg = pick_config(path, M, N, K, false);
+    p.split = split_plan(path, p.cfg, M, N, K, false);
+    const size_t planes_b = planes_of(p.cfg);
+    p.planes = avail >= planes_b ? planes_b : 0;
+    return p;
 }
 
 // split_ws: workspace for the partial products of a split-K plan (nullptr:
@@ -612,18 +644,21 @@ int choose_batched_variant(int path, int64_t M, int64_t N, int64_t K)
     return 0;                                  // 64 x 64
 }
 
+// Compute units of the current device, queried once per device.  Threads
+// that race on the first query each store the same value into an atomic
+// slot, so concurrent callers never read a torn or half-written entry.
 int device_cus()
 {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64];   // zero-initialised (static storage)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cus[dev] == 0) {
-        int n = 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
             n = 256;
-        cus[dev] = n;
+        cus[dev].store(n, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return n;
 }
 
 // Batched workspace: a 256-byte header holding the work-list counter, then
@@ -728,24 +763,15 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
         return run_fp8_packed(M, N, K, alpha, base + w.qa, base + w.sa, base + w.qb, base + w.sb,
                               beta, C, ldc, s);
     }
-    // Optional workspace uses, in this order: pre-packed BF16 planes, then the
-    // split-K partials; each is used only if the workspace still has room.
-    const int cfg = pick_config(path, M, N, K);
-    const SplitPlan plan = split_plan(path, cfg, M, N, K);
+    // Optional workspace uses: pre-packed 16-bit planes at its start, then
+    // the split-K partials (plan_gemm).
     uint8_t* ws = static_cast<uint8_t*>(workspace);
-    size_t left = (ws != nullptr && (reinterpret_cast<uintptr_t>(ws) & 255) == 0) ? workspace_bytes : 0;
-    void* planes = nullptr;
-    if (is_16bit(path) && uses_planes(path, cfg, M, N, K)) {
-        const size_t need = align256(bf16_workspace(path, M, N, K).total);
-        if (left >= need) {
-            planes = ws;
-            ws += need;
-            left -= need;
-        }
-    }
-    void* split_ws = (plan.splits > 1 && left >= plan.bytes) ? ws : nullptr;
-    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, cfg,
-                    plan, split_ws, planes);
+    const size_t avail = (ws != nullptr && (reinterpret_cast<uintptr_t>(ws) & 255) == 0) ? workspace_bytes : 0;
+    const GemmPlan gp = plan_gemm(path, M, N, K, avail);
+    void* planes = gp.planes ? ws : nullptr;
+    void* split_ws = gp.split.splits > 1 ? ws + gp.planes : nullptr;
+    return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, gp.cfg,
+                    gp.split, split_ws, planes);
 }
 
 int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
@@ -761,12 +787,31 @@ size_t mg_gemm_workspace_size(int path, char transA, char transB, int64_t M, int
     (void)transA; (void)transB;
     if (M <= 0 || N <= 0 || K <= 0 || !float_path(path) || beyond_int(M, N, K)) return 0;
     if (path == MG_PATH_FP8_T128) return K > kMaxFp8K ? 0 : fp8_workspace(M, N, K).total;
-    size_t total = 0;
-    const int cfg = pick_config(path, M, N, K);
-    if (is_16bit(path) && uses_planes(path, cfg, M, N, K))
-        total += align256(bf16_workspace(path, M, N, K).total);
-    total += split_plan(path, cfg, M, N, K).bytes;
-    return total;
+    const GemmPlan gp = plan_gemm(path, M, N, K, SIZE_MAX);
+    return gp.planes + gp.split.bytes;
+}
+
+int mg_gemm_plan(int path, int64_t M, int64_t N, int64_t K, size_t workspace_bytes, int* out3)
+{
+    if (!float_path(path)) return MG_ERR_UNSUPPORTED;
+    if (M < 0) return -2;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    if (out3 == nullptr) return -6;
+    if (beyond_int(M, N, K)) return MG_ERR_TOO_LARGE;
+    if (path == MG_PATH_FP8_T128) {
+        if (K > kMaxFp8K) return MG_ERR_TOO_LARGE;
+        out3[0] = pick_config(path, M, N, K);
+        out3[1] = 1;
+        out3[2] = 1;
+        return (M > 0 && N > 0 && K > 0 && workspace_bytes < fp8_workspace(M, N, K).total) ? MG_ERR_WORKSPACE
+                                                                                           : MG_OK;
+    }
+    const GemmPlan gp = plan_gemm(path, M, N, K, workspace_bytes);
+    out3[0] = gp.cfg;
+    out3[1] = gp.split.splits > 1 ? gp.split.splits : 1;
+    out3[2] = gp.planes ? 1 : 0;
+    return MG_OK;
 }
 
 int mg_fp8_packed_size(int64_t R, int64_t K, size_t* q_bytes, size_t* scale_bytes)

@@ -1,6 +1,6 @@
 #pragma once
 // FP32 GEMM tile WITHOUT packing: the "Tiling" strategy of Kuzma et al.
-// (SPE 2023, Section 4.1.2), next to the packed "Tiling+Packing" scheme of
+// (SPE 2023, Section 4.1.3), next to the packed "Tiling+Packing" scheme of
 // tile_f32.h.
 //
 // The GEMM loops are still tiled (workgroup tile, wave tile, an 8-deep K

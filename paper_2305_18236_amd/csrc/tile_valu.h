@@ -3,7 +3,7 @@
 // matrix cores: the GPU counterpart of the paper's "generic lowering" of the
 // matrix-multiply intrinsic to ordinary vector FMAs (Section 3.2), measured
 // against the matrix-core lowering as in its VSX-vs-MMA comparison
-// (Section 4.3).
+// (Section 4.4).
 //
 // The macro level is the one of tile_f32.h unchanged: the same BM x BN
 // workgroup tile, the same double-buffered k-major LDS panels written by the

@@ -109,6 +109,44 @@ def test_operand_layout_from_strides():
         operand_layout(torch.empty(4, 6)[:, ::2])
 
 
+def test_operand_layout_refuses_broadcast_views():
+    """A column (M x 1) or row (1 x N) expanded from one element has stride 0
+    along its long dimension: reading it with any ld >= 1 would run past the
+    one stored element, so it must be refused (the autograd layer then makes
+    a contiguous copy)."""
+    from paper_2305_18236_amd import operand_layout
+    from paper_2305_18236_amd.autograd import _as_operand
+    one = torch.ones(1, 1)
+    col = one.expand(6, 1)
+    row = one.expand(1, 6)
+    assert col.stride()[0] == 0 and row.stride()[1] == 0
+    for X in (col, row, torch.ones(1, 6).expand(4, 6), torch.ones(5, 1).expand(5, 3)):
+        with pytest.raises(ValueError):
+            operand_layout(X)
+        Y = _as_operand(X)
+        assert Y.is_contiguous() and torch.equal(Y, X)
+        assert operand_layout(Y) == ("N", max(X.shape[1], 1))
+    # overlapping rows (row stride below the row length) are refused too
+    with pytest.raises(ValueError):
+        operand_layout(torch.empty(20).as_strided((4, 6), (3, 1)))
+    # single rows and columns of real storage keep a valid ld
+    assert operand_layout(torch.empty(6, 1)) == ("N", 1)
+    assert operand_layout(torch.empty(1, 6)) == ("N", 6)
+    assert operand_layout(torch.empty(6, 1).t()) == ("N", 6)
+    assert operand_layout(torch.empty(3, 8)[:, :1]) == ("N", 8)
+
+
+def test_output_ld_refuses_overlapping_rows():
+    from paper_2305_18236_amd import output_ld
+    assert output_ld(torch.empty(5, 7)) == 7
+    assert output_ld(torch.empty(5, 12)[:, :7]) == 12
+    assert output_ld(torch.empty(1, 7)) == 7
+    with pytest.raises(ValueError):
+        output_ld(torch.zeros(1, 7).expand(5, 7))
+    with pytest.raises(ValueError):
+        output_ld(torch.zeros(5, 1).expand(5, 7))
+
+
 def _syr2k(native, **kw):
     a = dict(path=0, uplo="L", trans="N", N=4, K=6, alpha=1.0, A=FAKE, lda=6, B=FAKE, ldb=6, beta=0.0,
              C=FAKE, ldc=4)

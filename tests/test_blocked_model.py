@@ -35,26 +35,40 @@ def logical(buf, trans, rows, cols, ld):
     return stored.T
 
 
-def layered_gemm(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, cfg, splits=1):
-    """Algorithm 1's loops as the GPU runs them; returns C (M x N, float64)."""
+SPLIT_GRAIN = 128   # K ranges of a split are whole multiples of this (every BK divides it)
+
+
+def split_ranges(K, splits):
+    """The K ranges of a split-K launch, as the library cuts them: a range
+    length of ceil(K / splits) rounded up to a multiple of 128, so the last
+    range is the remainder and fewer than `splits` ranges can result."""
+    if splits < 2:
+        return [(0, K)]
+    chunk = -(-(-(-K // splits)) // SPLIT_GRAIN) * SPLIT_GRAIN
+    return [(k0, min(K, k0 + chunk)) for k0 in range(0, K, chunk)]
+
+
+def layered_gemm(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, cfg, splits=1, partials_out=None):
+    """Algorithm 1's loops as the GPU runs them; returns C (M x N, float64).
+    partials_out (a list), if given, receives each K range's unscaled M x N
+    partial product."""
     BM, BN, BK, WM, WN = cfg
     opA = logical(np.asarray(A, np.float64), tA, M, K, lda)
     opB = logical(np.asarray(B, np.float64), tB, K, N, ldb)
-    nk = math.ceil(K / BK)
-    chunk = math.ceil(nk / splits)              # panels per K range
+    ranges = split_ranges(K, splits)
     C = np.zeros((M, N))
+    full = [np.zeros((M, N)) for _ in ranges]
     for tm in range(math.ceil(M / BM)):
         for tn in range(math.ceil(N / BN)):
             m0, n0 = tm * BM, tn * BN
             partials = []
-            for s in range(splits):
+            for r, (ks, ke) in enumerate(ranges):
                 acc = np.zeros((BM, BN))
-                for kt in range(s * chunk, min(nk, (s + 1) * chunk)):
-                    k0 = kt * BK
+                for k0 in range(ks, ke, BK):
                     # pack both panels, zero outside the matrix
                     Ap = np.zeros((BM, BK))
                     Bp = np.zeros((BK, BN))
-                    mr, kr_, nr = min(BM, M - m0), min(BK, K - k0), min(BN, N - n0)
+                    mr, kr_, nr = min(BM, M - m0), min(BK, ke - k0), min(BN, N - n0)
                     Ap[:mr, :kr_] = opA[m0:m0 + mr, k0:k0 + kr_]
                     Bp[:kr_, :nr] = opB[k0:k0 + kr_, n0:n0 + nr]
                     # wave tiles, 32 x 32 accumulator blocks, rank-2 updates
@@ -65,6 +79,8 @@ def layered_gemm(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, cfg, splits=1
                                     for k in range(0, BK, 2):
                                         acc[i:i + 32, j:j + 32] += Ap[i:i + 32, k:k + 2] @ Bp[k:k + 2, j:j + 32]
                 partials.append(acc)
+                mr, nr = min(BM, M - m0), min(BN, N - n0)
+                full[r][m0:m0 + mr, n0:n0 + nr] = acc[:mr, :nr]
             total = partials[0]
             for p in partials[1:]:      # fixed order, as the reduction kernel sums them
                 total = total + p
@@ -73,6 +89,8 @@ def layered_gemm(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C0, cfg, splits=1
             if beta != 0.0:
                 out = out + beta * C0[m0:m0 + mr, n0:n0 + nr]
             C[m0:m0 + mr, n0:n0 + nr] = out
+    if partials_out is not None:
+        partials_out.extend(full)
     return C
 
 
@@ -112,17 +130,42 @@ def test_model_equals_oracle_on_integer_inputs(configs, cfg_id, M, N, K, tA, tB,
         assert np.array_equal(got, ref), (cfg, alpha, beta)
 
 
-@pytest.mark.parametrize("splits", [2, 3, 5])
-def test_split_k_ranges_sum_to_the_product(configs, splits):
-    M, N, K = 70, 45, 333
+@pytest.mark.parametrize("K,splits,expect", [
+    (333, 2, [(0, 256), (256, 333)]), (333, 3, [(0, 128), (128, 256), (256, 333)]),
+    (333, 5, [(0, 128), (128, 256), (256, 333)]),
+    (1000, 3, [(0, 384), (384, 768), (768, 1000)]), (1000, 4, [(0, 256), (256, 512), (512, 768), (768, 1000)]),
+    (4096, 16, [(256 * i, 256 * i + 256) for i in range(16)]), (300, 7, [(0, 128), (128, 256), (256, 300)]),
+])
+def test_split_k_ranges(configs, K, splits, expect):
+    """The model's K ranges are the library's: the count mg_split_count gives
+    under a forced split, range starts on multiples of 128 (so every panel
+    depth divides them), and each range's partial product equals the oracle's
+    product over exactly that K slice, bit for bit (integer inputs)."""
+    from paper_2305_18236_amd import _native
+    ranges = split_ranges(K, splits)
+    assert ranges == expect
+    assert _native.mg_force_splits(0, splits) == 0
+    try:
+        assert _native.mg_split_count(0, 70, 45, K) == len(ranges)
+    finally:
+        _native.mg_force_splits(0, -1)
+    M, N = 70, 45
     a = si.integers((M, K), 11)
     b = si.integers((K, N), 12)
     c0 = si.integers((M, N), 13)
     A, lda = si.store(a, "N")
     B, ldb = si.store(b, "T")
+    parts = []
+    got = layered_gemm("N", "T", M, N, K, 1.5, A, lda, B, ldb, 0.5, c0, configs[0], splits=splits,
+                       partials_out=parts)
     ref, _ = oracle.gemm("N", "T", M, N, K, 1.5, A, lda, B, ldb, 0.5, c0, N)
-    got = layered_gemm("N", "T", M, N, K, 1.5, A, lda, B, ldb, 0.5, c0, configs[0], splits=splits)
     assert np.array_equal(got, ref)
+    assert len(parts) == len(ranges)
+    for (ks, ke), part in zip(ranges, parts):
+        sa = np.ascontiguousarray(a[:, ks:ke])
+        sb = np.ascontiguousarray(b[ks:ke, :])
+        want, _ = oracle.gemm("N", "N", M, N, ke - ks, 1.0, sa, ke - ks, sb, N, 0.0, None, N)
+        assert np.array_equal(part, want), (ks, ke)
 
 
 def test_beta_zero_never_reads_c0_and_padding_never_read(configs):

@@ -370,6 +370,87 @@ def test_chain_grads_shapes_and_denominators():
         assert np.all(np.abs(g[k]) <= den[k] * (1 + 1e-12))
 
 
+def _brute_chain(X, W1, W2, G):
+    """Gradients of sum(((X W1) W2) * G) and their absolute-value chains, as
+    explicit sums over Python integers (exact): for H = X W1,
+      dW2[h][d] = sum_m H[m][h] G[m][d],  den = sum_{m,k} |X[m][k]||W1[k][h]||G[m][d]|
+      dW1[k][h] = sum_{m,d} X[m][k] G[m][d] W2[h][d],  den = the same over |.|
+      dX[m][k]  = sum_{h,d} G[m][d] W2[h][d] W1[k][h], den = the same over |.|"""
+    Xi, W1i, W2i, Gi = ([[int(v) for v in row] for row in a] for a in (X, W1, W2, G))
+    Mx, D = len(Xi), len(Xi[0])
+    Hd = len(W1i[0])
+    Do = len(W2i[0])
+    g = {"dW2": np.zeros((Hd, Do), dtype=object), "dW1": np.zeros((D, Hd), dtype=object),
+         "dX": np.zeros((Mx, D), dtype=object)}
+    den = {k: np.zeros(v.shape, dtype=object) for k, v in g.items()}
+    for h in range(Hd):
+        for d in range(Do):
+            for m in range(Mx):
+                for k in range(D):
+                    g["dW2"][h, d] += Xi[m][k] * W1i[k][h] * Gi[m][d]
+                    den["dW2"][h, d] += abs(Xi[m][k]) * abs(W1i[k][h]) * abs(Gi[m][d])
+    for k in range(D):
+        for h in range(Hd):
+            for m in range(Mx):
+                for d in range(Do):
+                    g["dW1"][k, h] += Xi[m][k] * Gi[m][d] * W2i[h][d]
+                    den["dW1"][k, h] += abs(Xi[m][k]) * abs(Gi[m][d]) * abs(W2i[h][d])
+    for m in range(Mx):
+        for k in range(D):
+            for h in range(Hd):
+                for d in range(Do):
+                    g["dX"][m, k] += Gi[m][d] * W2i[h][d] * W1i[k][h]
+                    den["dX"][m, k] += abs(Gi[m][d]) * abs(W2i[h][d]) * abs(W1i[k][h])
+    return g, den
+
+
+def test_chain_grads_and_denominators_equal_brute_force_sums():
+    """On small integers every sum is exact in FP64, so the oracle's gradients
+    AND its denominators must equal the explicit quadruple sums bit for bit.
+    Mixed signs make |dH| smaller than |G||W2|^T, so a denominator built on
+    the wrong chain (or any over-estimate) fails here."""
+    X = si.integers((5, 3), 185)
+    W1 = si.integers((3, 4), 186)
+    W2 = si.integers((4, 2), 187)
+    G = si.integers((5, 2), 188)
+    g, den = oracle.chain_grads(X, W1, W2, G)
+    bg, bden = _brute_chain(X, W1, W2, G)
+    for k in ("dX", "dW1", "dW2"):
+        assert np.array_equal(g[k], bg[k].astype(np.float64)), k
+        assert np.array_equal(den[k], bden[k].astype(np.float64)), k
+    # the inputs do cancel: at least one denominator exceeds |gradient| somewhere
+    assert any(np.any(den[k] > np.abs(g[k])) for k in g)
+
+
+def test_chain_denominators_equal_int64_chains():
+    """The three denominators are the chains |X|^T (|G||W2|^T), (|X||W1|)^T |G|
+    and (|G||W2|^T) |W1|^T, checked against numpy's int64 products at a size
+    whose sums are still exact in FP64 (entries <= 8, sums < 2^53)."""
+    X = si.integers((40, 24), 191).astype(np.int64)
+    W1 = si.integers((24, 48), 192).astype(np.int64)
+    W2 = si.integers((48, 16), 193).astype(np.int64)
+    G = si.integers((40, 16), 194).astype(np.int64)
+    _, den = oracle.chain_grads(X.astype(np.float32), W1.astype(np.float32), W2.astype(np.float32),
+                                G.astype(np.float32))
+    aX, aW1, aW2, aG = np.abs(X), np.abs(W1), np.abs(W2), np.abs(G)
+    aGW2 = aG @ aW2.T
+    assert np.array_equal(den["dW1"], (aX.T @ aGW2).astype(np.float64))
+    assert np.array_equal(den["dW2"], ((aX @ aW1).T @ aG).astype(np.float64))
+    assert np.array_equal(den["dX"], (aGW2 @ aW1.T).astype(np.float64))
+
+
+def test_chain_denominators_equal_gradients_for_nonnegative_inputs():
+    """With every input >= 0 the absolute values change nothing, so each
+    denominator is its gradient exactly (integers: exact sums)."""
+    X = np.abs(si.integers((9, 4), 195))
+    W1 = np.abs(si.integers((4, 7), 196))
+    W2 = np.abs(si.integers((7, 3), 197))
+    G = np.abs(si.integers((9, 3), 198))
+    g, den = oracle.chain_grads(X, W1, W2, G)
+    for k in g:
+        assert np.array_equal(g[k], den[k]), k
+
+
 # ------------------------------------------------------------------ FP16 ----
 
 def test_fp16_round_matches_library_conversion():

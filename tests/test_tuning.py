@@ -222,3 +222,50 @@ def test_fp8_big_tile_threshold(native):
     assert native.mg_tuned_config(3, 8192, 8192, 8192) == 7
     assert native.mg_tuned_config(5, 3072, 3072, 3072) == 5     # INT8, 144 tiles
     assert native.mg_tuned_config(5, 4096, 2048, 8192) == 4     # INT8, 128 tiles
+
+
+def test_plan_without_workspace_is_chosen_for_an_unsplit_k_loop(native):
+    """mg_sgemm passes no workspace.  Its tile must be the best one for an
+    unsplit K loop, not the split plan's tile run unsplit: at 6144^3 the split
+    plan takes 256 x 256 tiles in four K ranges, while unsplit 128 x 128
+    tiles fill the compute units' rounds better (the round plan's model puts
+    256 x 256 unsplit at about 4.5 ms against 3.7 ms)."""
+    n = 6144
+    full = native.mg_gemm_workspace_size(0, "N", "N", n, n, n)
+    assert full > 0
+    assert native.mg_gemm_plan(0, n, n, n, full) == (0, 5, 4, 0)
+    st, cfg, splits, packed = native.mg_gemm_plan(0, n, n, n, 0)
+    assert (st, splits, packed) == (0, 1, 0)
+    assert cfg == 0
+    # one byte short of the split's partials: planned as if no split existed
+    assert native.mg_gemm_plan(0, n, n, n, full - 1) == (0, cfg, 1, 0)
+
+
+SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (1536, 1536, 1536), (3072, 3072, 3072), (8192, 8192, 256),
+          (256, 8192, 8192), (16384, 1024, 4096), (64, 96, 2048), (512, 512, 8192), (8192, 8192, 8192)]
+
+
+@pytest.mark.parametrize("path", [0, 1, 2, 4])
+@pytest.mark.parametrize("M,N,K", SHAPES)
+def test_plan_matches_queries_and_never_splits_without_room(native, path, M, N, K):
+    full = native.mg_gemm_workspace_size(path, "N", "N", M, N, K)
+    st, cfg, splits, packed = native.mg_gemm_plan(path, M, N, K, full)
+    assert st == 0
+    assert cfg == native.mg_tuned_config(path, M, N, K)
+    assert splits == native.mg_split_count(path, M, N, K)
+    st, cfg0, s0, p0 = native.mg_gemm_plan(path, M, N, K, 0)
+    assert st == 0 and s0 == 1 and p0 == 0
+    if splits == 1 and not packed:
+        assert full == 0 and cfg0 == cfg
+
+
+def test_plan_argument_errors(native):
+    assert native.mg_gemm_plan(7, 8, 8, 8, 0)[0] == -101
+    assert native.mg_gemm_plan(0, -1, 8, 8, 0)[0] == -2
+    assert native.mg_gemm_plan(0, 8, -1, 8, 0)[0] == -3
+    assert native.mg_gemm_plan(0, 8, 8, -1, 0)[0] == -4
+    assert native.mg_gemm_plan(0, 2 ** 40, 8, 8, 0)[0] == -102
+    # FP8 needs its packing workspace
+    need = native.mg_gemm_workspace_size(3, "N", "N", 512, 512, 512)
+    assert native.mg_gemm_plan(3, 512, 512, 512, need)[0] == 0
+    assert native.mg_gemm_plan(3, 512, 512, 512, need - 1)[0] == -100
