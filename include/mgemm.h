@@ -320,6 +320,19 @@ int mg_gemm_batched_timed(int path, int64_t count, const mg_problem *problems,
 int64_t mg_wall_clock_hz(void);
 
 /*
+ * The shader (core) clock the GPU runs at, for reporting a measured clock
+ * beside a fraction of the spec peak (which assumes 2.4 GHz).  Launches a
+ * probe of 16 one-wave workgroups on `stream`, behind the work already
+ * queued there, each timing `microseconds` of the constant-rate wall clock
+ * against the shader-cycle counter; waits for the stream (this call
+ * synchronises, unlike the GEMMs) and stores the average clock in MHz in
+ * *mhz.  Launched right behind a timed workload, it reads the clock as that
+ * workload ends.  Concurrent calls are serialised.  Errors: -2 microseconds
+ * outside [1, 10^6], -3 mhz NULL, MG_ERR_HIP - e for a runtime error.
+ */
+int mg_shader_clock_mhz(void *stream, int64_t microseconds, double *mhz);
+
+/*
  * The pack-stage conversion of the BF16 paths on its own (Table 1's bf16
  * operand type, round to nearest even): hi[t] = bf16(x[t]) and, when lo is
  * not NULL, lo[t] = bf16(x[t] - hi[t]), as raw bf16 bit patterns.  x, hi, lo

@@ -16,6 +16,7 @@ library conversions, invariants).
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 import subprocess
 
@@ -287,6 +288,44 @@ def chain_grads(X, W1, W2, G, threads=None):
     return {"dX": dX, "dW1": dW1, "dW2": dW2}, den
 
 
+def chain_entries(X, W1, W2, G, n=16, seed=0, threads=None):
+    """Y and the three gradients of chain_grads at sampled entries, with their
+    chained denominators, from oracle GEMMs on slices of the operands only
+    (the same definitions restricted to the sampled rows and columns, so a
+    full-size chain needs no full-size FP64 product).  Returns
+    {name: (I, J, values at (I x J), denominators at (I x J))} for Y, dX, dW1
+    and dW2, n row indices I and n column indices J each, drawn without
+    replacement from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    X, W1, W2, G = (_f64(a) for a in (X, W1, W2, G))
+    Mx, D = X.shape
+    Hd = W1.shape[1]
+    aX, aW1, aW2, aG = (np.abs(a) for a in (X, W1, W2, G))
+    gl = functools.partial(gemm_logical, threads=threads)
+    out = {}
+    # dW2[i, j] = sum_m H[m, i] G[m, j], with H[:, i] = X W1[:, i]
+    I = rng.choice(Hd, min(n, Hd), replace=False)
+    J = rng.choice(D, min(n, D), replace=False)
+    H_I, aH_I = gl(X, W1[:, I])[0], gl(aX, aW1[:, I])[0]
+    out["dW2"] = (I, J, gl(H_I.T, G[:, J])[0], gl(aH_I.T, aG[:, J])[0])
+    # dW1[i, j] = sum_m X[m, i] dH[m, j], with dH[:, j] = G W2[j, :]^T
+    I = rng.choice(D, min(n, D), replace=False)
+    J = rng.choice(Hd, min(n, Hd), replace=False)
+    dH_J, adH_J = gl(G, W2[J, :].T)[0], gl(aG, aW2[J, :].T)[0]
+    out["dW1"] = (I, J, gl(X[:, I].T, dH_J)[0], gl(aX[:, I].T, adH_J)[0])
+    # dX[i, j] = sum_h dH[i, h] W1[j, h], with dH[i, :] = G[i, :] W2^T
+    I = rng.choice(Mx, min(n, Mx), replace=False)
+    J = rng.choice(D, min(n, D), replace=False)
+    dH_I, adH_I = gl(G[I, :], W2.T)[0], gl(aG[I, :], aW2.T)[0]
+    out["dX"] = (I, J, gl(dH_I, W1[J, :].T)[0], gl(adH_I, aW1[J, :].T)[0])
+    # Y[i, j] = (X W1)[i, :] W2[:, j]; its denominator (|X||W1|)|W2|
+    I = rng.choice(Mx, min(n, Mx), replace=False)
+    J = rng.choice(W2.shape[1], min(n, W2.shape[1]), replace=False)
+    H_rows, aH_rows = gl(X[I, :], W1)[0], gl(aX[I, :], aW1)[0]
+    out["Y"] = (I, J, gl(H_rows, W2[:, J])[0], gl(aH_rows, aW2[:, J])[0])
+    return out
+
+
 # ----------------------------------------------------------------- INT8 ----
 
 def gemm_i8(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta=0, C0=None, ldc0=None, threads=None):
@@ -329,3 +368,19 @@ def syr2k(uplo, trans, N, K, alpha, A, lda, B, ldb, beta=0.0, C0=None, ldc=None,
     _load().oracle_syr2k(_tchar(uplo), _tchar(trans), N, K, float(alpha), _p(A64), lda, _p(B64), ldb,
                          float(beta), _p(C), ldc, _p(D), _threads(threads))
     return C, D.reshape(max(N, 1), max(N, 1))[:N, :N]
+
+
+def syr2k_entries(trans, K, alpha, A, lda, B, ldb, beta, C0, ldc0, I, J, threads=None):
+    """The SYR2K of Section 5.1 at given entries (i, j) only, with its error
+    denominator: C[i][j] = alpha*(op(X) op(Y)^T)[i][j] + alpha*(op(Y) op(X)^T)[i][j]
+    + beta*C0[i][j], D = |alpha| sum_k (|x_ik||y_jk| + |y_ik||x_jk|) + |beta||C0[i][j]|,
+    where op(X) is A (trans 'N', stored N x K) or A^T ('T', stored K x N), and
+    likewise op(Y) from B.  Built from the oracle's GEMM entries: the first
+    product carries beta*C0, the second is added in FP64 (one extra rounding,
+    far below every tolerance).  Which triangle (i, j) lies in is the caller's
+    choice; the value does not depend on it."""
+    t1 = "N" if _tchar(trans) == b"N" else "T"
+    t2 = "T" if t1 == "N" else "N"
+    c1, d1 = gemm_entries(t1, t2, K, alpha, A, lda, B, ldb, beta, C0, ldc0, I, J, threads=threads)
+    c2, d2 = gemm_entries(t1, t2, K, alpha, B, ldb, A, lda, 0.0, None, ldc0, I, J, threads=threads)
+    return c1 + c2, d1 + d2

@@ -115,6 +115,8 @@ def lib():
     L.mg_gemm_batched_timed.restype = ci
     L.mg_wall_clock_hz.argtypes = []
     L.mg_wall_clock_hz.restype = i64
+    L.mg_shader_clock_mhz.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+    L.mg_shader_clock_mhz.restype = ci
     L.mg_status_string.argtypes = [ci]
     L.mg_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -293,3 +295,10 @@ def mg_gemm_plan(path, M, N, K, workspace_bytes):
     out = (ctypes.c_int * 3)()
     st = int(lib().mg_gemm_plan(int(path), M, N, K, int(workspace_bytes), out))
     return st, int(out[0]), int(out[1]), int(out[2])
+
+
+def mg_shader_clock_mhz(stream, microseconds=50):
+    """(status, MHz): the shader clock measured by a probe queued on `stream`."""
+    out = ctypes.c_double(0.0)
+    st = int(lib().mg_shader_clock_mhz(stream, int(microseconds), ctypes.byref(out)))
+    return st, float(out.value)

@@ -108,6 +108,12 @@ inline unsigned split_count(const GemmArgs& g)
     return g.k_chunk > 0 ? unsigned((g.K + g.k_chunk - 1) / g.k_chunk) : 1u;
 }
 
+// Average shader clock (MHz) of a few compute units over `wall_ticks` of the
+// constant-rate wall clock (wall_hz ticks per second), measured by a probe
+// launched on `stream` behind the work already queued there; waits for the
+// stream.
+hipError_t measure_sclk(hipStream_t stream, int64_t wall_ticks, double wall_hz, double* mhz);
+
 // Sums the `splits` partials of g.part into C with g.alpha / g.beta.
 hipError_t launch_splitk_reduce(const GemmArgs& g, int splits, float* C, int64_t ldc, hipStream_t stream);
 

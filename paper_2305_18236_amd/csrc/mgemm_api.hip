@@ -1220,6 +1220,16 @@ int64_t mg_wall_clock_hz(void)
     return int64_t(khz) * 1000;
 }
 
+int mg_shader_clock_mhz(void* stream, int64_t microseconds, double* mhz)
+{
+    if (microseconds < 1 || microseconds > 1000000) return -2;
+    if (mhz == nullptr) return -3;
+    const int64_t hz = mg_wall_clock_hz();
+    if (hz <= 0) return MG_ERR_HIP - int(hipErrorNoDevice);
+    const int64_t ticks = std::max<int64_t>(1, hz * microseconds / 1000000);
+    return hip_status(mg::measure_sclk(reinterpret_cast<hipStream_t>(stream), ticks, double(hz), mhz));
+}
+
 const char* mg_status_string(int status)
 {
     switch (status) {

@@ -92,41 +92,6 @@ def test_backward_reads_transposed_layouts_without_copies(gpu):
     assert torch.equal(A.grad, dA_ref) and torch.equal(B.grad, dB_ref)
 
 
-def _sampled_chain_oracle(X, W1, W2, G, n=16, seed=0):
-    """FP64 oracle values of Y and of the three gradients at sampled entries,
-    with their chained denominators, from sliced oracle GEMMs only."""
-    rng = np.random.default_rng(seed)
-    Mx, D = X.shape
-    Hd = W1.shape[1]
-    aX, aW1, aW2, aG = (np.abs(a.astype(np.float64)) for a in (X, W1, W2, G))
-    out = {}
-    # dW2[i, j] = sum_m H[m, i] G[m, j],  H[:, i] = X W1[:, i]
-    I = rng.choice(Hd, n, replace=False)
-    J = rng.choice(D, n, replace=False)
-    H_I, _ = oracle.gemm_logical(X, W1[:, I])
-    aH_I, _ = oracle.gemm_logical(aX, aW1[:, I])
-    out["dW2"] = (I, J, oracle.gemm_logical(H_I.T, G[:, J])[0], oracle.gemm_logical(aH_I.T, aG[:, J])[0])
-    # dW1[i, j] = sum_m X[m, i] dH[m, j],  dH[:, j] = G W2[j, :]^T
-    I = rng.choice(D, n, replace=False)
-    J = rng.choice(Hd, n, replace=False)
-    dH_J, _ = oracle.gemm_logical(G, W2[J, :].T)
-    adH_J, _ = oracle.gemm_logical(aG, aW2[J, :].T)
-    out["dW1"] = (I, J, oracle.gemm_logical(X[:, I].T, dH_J)[0], oracle.gemm_logical(aX[:, I].T, adH_J)[0])
-    # dX[i, j] = sum_h dH[i, h] W1[j, h],  dH[i, :] = G[i, :] W2^T
-    I = rng.choice(Mx, n, replace=False)
-    J = rng.choice(D, n, replace=False)
-    dH_I, _ = oracle.gemm_logical(G[I, :], W2.T)
-    adH_I, _ = oracle.gemm_logical(aG[I, :], aW2.T)
-    out["dX"] = (I, J, oracle.gemm_logical(dH_I, W1[J, :].T)[0], oracle.gemm_logical(adH_I, aW1[J, :].T)[0])
-    # Y[i, j] = (X W1)[i, :] W2[:, j]
-    I = rng.choice(Mx, n, replace=False)
-    J = rng.choice(D, n, replace=False)
-    H_rows, _ = oracle.gemm_logical(X[I, :], W1)
-    aH_rows, _ = oracle.gemm_logical(aX[I, :], aW1)
-    out["Y"] = (I, J, oracle.gemm_logical(H_rows, W2[:, J])[0], oracle.gemm_logical(aH_rows, aW2[:, J])[0])
-    return out
-
-
 @pytest.mark.slow
 def test_full_size_chain_sampled(gpu):
     """X 4096x2048, W1 2048x8192, W2 8192x2048, bf16x3 forward and backward;
@@ -134,7 +99,7 @@ def test_full_size_chain_sampled(gpu):
     chained denominators (two stacked GEMMs: 2 x 1e-5)."""
     X, W1, W2, G = _chain_inputs(4096, 2048, 8192)
     Y, g = _gpu_grads(X, W1, W2, G, gpu, "bf16x3")
-    samples = _sampled_chain_oracle(X, W1, W2, G)
+    samples = oracle.chain_entries(X, W1, W2, G)
     for name, (I, J, ref, den) in samples.items():
         got = Y[np.ix_(I, J)].astype(np.float64) if name == "Y" else g[name][np.ix_(I, J)]
         err = oracle.normalized_error(got, ref, den)

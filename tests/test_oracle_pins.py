@@ -439,6 +439,27 @@ def test_chain_denominators_equal_int64_chains():
     assert np.array_equal(den["dX"], (aGW2 @ aW1.T).astype(np.float64))
 
 
+def test_chain_entries_equal_the_full_chain():
+    """chain_entries (sliced oracle GEMMs) equals chain_grads / chain_forward
+    and their denominators at its sampled entries, bit for bit on integer
+    inputs, where every sum is exact whatever the slicing."""
+    X = si.integers((12, 5), 201)
+    W1 = si.integers((5, 9), 202)
+    W2 = si.integers((9, 5), 203)
+    G = si.integers((12, 5), 204)
+    g, den = oracle.chain_grads(X, W1, W2, G)
+    H, Y = oracle.chain_forward(X, W1, W2)
+    aH, aY = oracle.chain_forward(np.abs(X), np.abs(W1), np.abs(W2))
+    full = dict(g, Y=Y)
+    fden = dict(den, Y=aY)
+    got = oracle.chain_entries(X, W1, W2, G, n=4, seed=3)
+    assert sorted(got) == ["Y", "dW1", "dW2", "dX"]
+    for k, (I, J, vals, dens) in got.items():
+        assert len(set(I)) == len(I) and len(set(J)) == len(J)
+        assert np.array_equal(vals, full[k][np.ix_(I, J)]), k
+        assert np.array_equal(dens, fden[k][np.ix_(I, J)]), k
+
+
 def test_chain_denominators_equal_gradients_for_nonnegative_inputs():
     """With every input >= 0 the absolute values change nothing, so each
     denominator is its gradient exactly (integers: exact sums)."""
@@ -619,3 +640,24 @@ def test_syr2k_equal_operands_closed_form():
     ref = 1.5 * 2 * (Xi @ Xi.T) + 0.5 * C0
     up = np.triu_indices(N)
     assert np.array_equal(C.reshape(N, N)[up], ref[up])
+
+
+@pytest.mark.parametrize("trans", ["N", "T"])
+def test_syr2k_entries_equal_the_full_syr2k(trans):
+    """syr2k_entries (two oracle GEMM entry sums) equals the full SYR2K oracle
+    and its denominator at sampled entries of both triangles: bit for bit on
+    integer inputs, where the one extra FP64 addition is exact."""
+    N, K = 23, 17
+    shape = (N, K) if trans == "N" else (K, N)
+    A = si.integers(shape, 211 + (trans == "T"))
+    B = si.integers(shape, 213 + (trans == "T"))
+    C0 = si.integers((N, N), 215)
+    lda = ldb = shape[1]
+    I, J = si.sample_indices(N, N, 60, 216)
+    vals, dens = oracle.syr2k_entries(trans, K, 1.5, A, lda, B, ldb, -0.5, C0, N, I, J)
+    for uplo in "LU":
+        full, D = oracle.syr2k(uplo, trans, N, K, 1.5, A, lda, B, ldb, -0.5, C0)
+        full = full.reshape(N, N)
+        tri = (I >= J) if uplo == "L" else (I <= J)
+        assert np.array_equal(vals[tri], full[I[tri], J[tri]])
+        assert np.array_equal(dens[tri], D[I[tri], J[tri]])
