@@ -83,6 +83,7 @@ enum mg_status {
     MG_ERR_UNSUPPORTED = -101,  /* unknown path or configuration id           */
     MG_ERR_TOO_LARGE = -102,    /* a dimension exceeds what the kernels index  */
     MG_ERR_BAD_TABLE = -103,    /* tuning table unreadable or malformed        */
+    MG_ERR_SCRATCH = -104,      /* needs more than MG_NOALLOC_SCRATCH_BYTES    */
     MG_ERR_HIP = -1000          /* MG_ERR_HIP - hipError_t                     */
 };
 
@@ -136,6 +137,32 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
             float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
             float beta, float *C, int64_t ldc,
             void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Allocation-free GEMM, for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, semantics and error
+ * codes as mg_gemm without the workspace: the library uses instead a fixed
+ * scratch buffer of MG_NOALLOC_SCRATCH_BYTES (256 MiB) of device memory that
+ * each GPU it runs on holds from the first call on that device until the
+ * process ends.  The call allocates and frees nothing.  The plan is the one
+ * mg_gemm makes for a workspace of that size (mg_gemm_plan with
+ * MG_NOALLOC_SCRATCH_BYTES), so results equal mg_gemm's with such a
+ * workspace bit for bit; on the non-FP8 paths a problem whose best plan
+ * needs more scratch runs the plan made without a K split (and converts the
+ * 16-bit operands inside the GEMM if their planes do not fit either).
+ * MG_PATH_FP8_T128 needs its packed operands in the scratch and returns
+ * MG_ERR_SCRATCH when they exceed it (about (M + N) K > 2^28 bytes).
+ * Every call on one GPU shares that GPU's scratch, which keeps whatever the
+ * last call left there (no call depends on its contents: everything read
+ * from it is written first by the same call).  Calls that overlap in time
+ * on one GPU (other streams, other host threads) race on the scratch and
+ * must be serialised by the caller, e.g. by issuing them on one stream.
+ */
+#define MG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int mg_gemm_noalloc(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
+                    float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                    float beta, float *C, int64_t ldc, void *stream);
 
 /* Workspace bytes mg_gemm uses for this problem with the current selection
  * state (forced configuration, tuning table, forced split; 0 when none). */

@@ -55,6 +55,8 @@ def lib():
     L.mg_gemm.argtypes = [ci, ch, ch, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp,
                           ctypes.c_size_t, vp]
     L.mg_gemm.restype = ci
+    L.mg_gemm_noalloc.argtypes = [ci, ch, ch, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]
+    L.mg_gemm_noalloc.restype = ci
     L.mg_gemm_workspace_size.argtypes = [ci, ch, ch, i64, i64, i64]
     L.mg_gemm_workspace_size.restype = ctypes.c_size_t
     L.mg_num_configs.argtypes = [ci]
@@ -158,6 +160,11 @@ def mg_gemm(path, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
             workspace, workspace_bytes, stream) -> int:
     return lib().mg_gemm(int(path), _c(transA), _c(transB), M, N, K, alpha, A, lda, B, ldb, beta,
                          C, ldc, workspace, workspace_bytes, stream)
+
+
+def mg_gemm_noalloc(path, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream) -> int:
+    return lib().mg_gemm_noalloc(int(path), _c(transA), _c(transB), M, N, K, alpha, A, lda, B, ldb, beta,
+                                 C, ldc, stream)
 
 
 def mg_gemm_workspace_size(path, transA, transB, M, N, K) -> int:

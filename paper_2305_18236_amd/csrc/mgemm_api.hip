@@ -727,6 +727,44 @@ Syr2kPlan syr2k_plan(int64_t N, int64_t K)
     return p;
 }
 
+// ---- Allocation-free GEMM (mg_gemm_noalloc): a fixed scratch buffer in
+// device memory stands in for the caller's workspace.  The array is a
+// file-scope device variable, so each GPU the library runs on holds its own
+// copy for the life of the process.  Host code never uses the array's name
+// as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that pointer is passed to kernels.
+constexpr size_t kScratchBytes = MG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mutex;
+
+// Device address of the current device's scratch, or nullptr with *err set.
+void* scratch_ptr(hipError_t* err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+        return nullptr;
+    }
+    void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p != nullptr) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (p == nullptr) {
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+    return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -772,6 +810,27 @@ int mg_gemm(int path, char transA, char transB, int64_t M, int64_t N, int64_t K,
     void* split_ws = gp.split.splits > 1 ? ws + gp.planes : nullptr;
     return run_gemm(path, is_t(transA), is_t(transB), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, gp.cfg,
                     gp.split, split_ws, planes);
+}
+
+int mg_gemm_noalloc(int path, char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+                    const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+                    int64_t ldc, void* stream)
+{
+    const int st = validate(transA, transB, M, N, K, A, lda, B, ldb, C, ldc);
+    if (st != MG_OK) return st;
+    if (!float_path(path)) return MG_ERR_UNSUPPORTED;
+    if (path == MG_PATH_FP8_T128) {
+        if (K > kMaxFp8K) return MG_ERR_TOO_LARGE;
+        // the packed FP8 operands are required, and must fit the scratch
+        if (M > 0 && N > 0 && K > 0 && alpha != 0.f && fp8_workspace(M, N, K).total > kScratchBytes)
+            return MG_ERR_SCRATCH;
+    }
+    if (M == 0 || N == 0) return MG_OK;
+    hipError_t e = hipSuccess;
+    void* ws = scratch_ptr(&e);
+    if (ws == nullptr) return hip_status(e);
+    // the plan mg_gemm makes for a workspace of kScratchBytes (plan_gemm)
+    return mg_gemm(path, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, kScratchBytes, stream);
 }
 
 int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
@@ -1249,6 +1308,7 @@ const char* mg_status_string(int status)
     case MG_ERR_UNSUPPORTED: return "unsupported path or configuration";
     case MG_ERR_TOO_LARGE: return "dimension too large for the kernels";
     case MG_ERR_BAD_TABLE: return "tuning table unreadable or malformed";
+    case MG_ERR_SCRATCH: return "problem needs more than the allocation-free entry point's scratch memory";
     default: break;
     }
     if (status <= MG_ERR_HIP) return hipGetErrorString(hipError_t(MG_ERR_HIP - status));
