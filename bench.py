@@ -13,9 +13,14 @@ Every workload prints one JSON line.  Each timed case carries:
   * its error against the FP64 oracle (max |C - C_ref| / (|alpha||A||B| +
     |beta||C0|) over sampled outputs, corners included; INT8: the number of
     sampled outputs that differ from the exact integer oracle);
-  * the shader clock measured by a probe queued right behind its timed steps
-    (the spec peaks assume 2.4 GHz; under sustained matrix work the chip runs
-    slower);
+  * the shader clock (the spec peaks assume 2.4 GHz; under sustained matrix
+    work the chip runs slower), from a probe of 16 one-wave workgroups that
+    times the shader-cycle counter against the constant-rate wall clock:
+    "during" runs on a second stream while the timed steps are still
+    executing (null when the GPU gave it no room before they ended) and
+    "after" runs queued right behind them (the clock recovers within
+    microseconds of the load ending, so "after" reads high); lists of
+    clocks hold one [during, after] pair per timed block;
   * the median and the 95 % confidence interval of its per-step times.
 The cases of a workload run in an order shuffled per round (the paper's
 randomised run order, Section 4.1.4) by a seeded generator whose seed is
@@ -112,6 +117,11 @@ def tflops(flops, ms):
     return flops / (ms * 1e-3) / 1e12
 
 
+def progress(msg):
+    """One line on stderr as a phase of the run ends (the JSON line is the only stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 # ---------------------------------------------------------------- timing ---
 
 class Bench:
@@ -121,6 +131,9 @@ class Bench:
         self.args, self.torch, self.native, self.dev = args, torch, native, dev
         self.stream = torch.cuda.current_stream()
         self.sp = self.stream.cuda_stream
+        # a second stream (default priority, like the first) for the clock
+        # probe that runs beside the timed steps
+        self.side = torch.cuda.Stream(device=dev)
         seed = args.order_seed if args.order_seed is not None else int.from_bytes(os.urandom(4), "little")
         self.order_seed = seed
         self.rng = random.Random(seed)
@@ -149,18 +162,27 @@ class Bench:
                 self.torch.cuda.synchronize()
         self.torch.cuda.synchronize()
 
-    def steps(self, fn, steps):
+    def steps(self, fn, steps, probe=False):
         """`steps` back-to-back calls with a HIP event between consecutive
-        calls on the launch stream; returns (per-step ms list, total ms)."""
+        calls on the launch stream; returns (per-step ms list, total ms,
+        clock during the steps).  probe: once the steps are queued, the clock
+        probe runs on the side stream, beside them when the GPU has room for
+        its 16 one-wave workgroups; its reading counts as taken during the
+        steps only if the launch stream is still busy when it returns."""
         torch = self.torch
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         ev[0].record(self.stream)
         for i in range(steps):
             fn()
             ev[i + 1].record(self.stream)
+        during = None
+        if probe:
+            st, mhz = self.native.mg_shader_clock_mhz(self.side.cuda_stream, 100)
+            if st == 0 and not self.stream.query():
+                during = round(mhz, 1)
         torch.cuda.synchronize()
         per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
-        return per, ev[0].elapsed_time(ev[steps])
+        return per, ev[0].elapsed_time(ev[steps]), during
 
     def per_launch(self, fn, steps, between=None):
         """Per-call times from an event pair around each call (for launches of
@@ -186,8 +208,8 @@ class Bench:
         steps = self.args.steps if steps is None else steps
         warmup = self.args.warmup if warmup is None else warmup
         self.warm(fn, warmup)
-        per, total = self.steps(fn, steps)
-        return {"per_ms": per, "total_ms": total, "sclk_mhz": self.sclk()}
+        per, total, during = self.steps(fn, steps, probe=True)
+        return {"per_ms": per, "total_ms": total, "sclk_mhz": self.sclk(), "sclk_mhz_during": during}
 
     def gemm_call(self, path, tA, tB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws=None):
         """A closure launching mg_gemm with its full workspace (allocated here once)."""
@@ -332,6 +354,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
     bench = Bench(args, torch, _native, dev)
+    progress(f"workload {args.workload}, order seed {bench.order_seed}")
     fn = {"sgemm": bench_sgemm, "batched": bench_batched, "chain": bench_chain, "mixed": bench_mixed,
           "fp8": bench_mixed, "sweep": bench_sweep, "tiling": bench_tiling, "engine": bench_engine,
           "types": bench_types, "syr2k": bench_syr2k, "smallk": bench_smallk}[args.workload]
@@ -379,6 +402,7 @@ def bench_sgemm(bench, si):
                        "algorithmic_flops_per_launch": flops}
     out["step_time_ms"] = {p: stats(r["per_ms"]) for p, r in res.items()}
     out["sclk_mhz"] = {p: r["sclk_mhz"] for p, r in res.items()}
+    out["sclk_mhz_during"] = {p: r["sclk_mhz_during"] for p, r in res.items()}
     if f32["sclk_mhz"]:
         out["pct_fp32_mfma_peak_at_measured_clock"] = round(
             100.0 * tflops(flops, ms) / (peak * f32["sclk_mhz"] / 2400.0), 2)
@@ -409,6 +433,7 @@ def bench_sgemm(bench, si):
     c1 = dC1.cpu().numpy().astype(np.float64)
 
     # ---- oracle leg
+    progress("GPU timing done; oracle leg")
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(A_h, B_h, C0_h, outs)
         out["cpu_baseline"] = cb
@@ -452,7 +477,8 @@ def bench_sweep(bench, si):
     cases = [("fp32", s, tA + tB) for s in SWEEP_SHAPES for tA in "NT" for tB in "NT"]
     cases += [("bf16x3", s, "NN") for s in SWEEP_SHAPES]
     runs, samples, clocks = {}, {c: [] for c in cases}, {c: [] for c in cases}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for case in bench.shuffled(cases):
             path, (m, n, k), lay = case
             A_h, B_h, C0_h, A, B, C0, C = data[(m, n, k)]
@@ -462,7 +488,7 @@ def bench_sweep(bench, si):
                 runs[case] = bench.gemm_call(path, lay[0], lay[1], m, n, k, ALPHA, A, lda, B, ldb, BETA, C, n)
             r = bench.case(runs[case])
             samples[case] += r["per_ms"]
-            clocks[case].append(r["sclk_mhz"])
+            clocks[case].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     rows = []
     for case in cases:
         path, (m, n, k), lay = case
@@ -539,7 +565,8 @@ def bench_mixed(bench, si):
     torch.cuda.synchronize()
     runs, per, clk = {}, {c: [] for c in cases}, {c: [] for c in cases}
     ws = None
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for case in bench.shuffled(cases):
             dist, p = case
             if case not in runs:
@@ -553,7 +580,7 @@ def bench_mixed(bench, si):
                     ws = runs[case].workspace
             r = bench.case(runs[case])
             per[case] += r["per_ms"]
-            clk[case].append(r["sclk_mhz"])
+            clk[case].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     flops = 2.0 * M * N * K
     I, J = si.sample_indices(M, N, SAMPLES, 303)
     rows = {}
@@ -659,12 +686,13 @@ def bench_batched(bench, si):
     cases = [(p, kind) for p in ("fp32", "bf16x3") for kind in ("persistent", "host_loop")]
     per = {c: [] for c in cases}
     clk = {c: [] for c in cases}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for case in bench.shuffled(cases):
             path, kind = case
             r = bench.case(persistent(path) if kind == "persistent" else loop(path))
             per[case] += r["per_ms"]
-            clk[case].append(r["sclk_mhz"])
+            clk[case].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     for path in ("fp32", "bf16x3"):
         # device time of one launch per problem: each launch between its own events
         fns = [one(path, i) for i in range(len(ops))]
@@ -767,11 +795,12 @@ def bench_chain(bench, si):
 
     per = {p: [] for p in ("bf16x3", "fp32")}
     clk = {p: [] for p in per}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for path in bench.shuffled(per):
             r = bench.case(step_fn(path))
             per[path] += r["per_ms"]
-            clk[path].append(r["sclk_mhz"])
+            clk[path].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     out["paths"] = {}
     for path in per:
         step_fn(path)()
@@ -806,6 +835,7 @@ def bench_tiling(bench, si):
     ncfg = native.mg_num_configs(0)
     rows = []
     for n in TILING_SIZES:
+        progress(f"size {n}")
         a = si.uniform((n * n,), si.seed_for(2, "A"))
         b = si.uniform((n * n,), si.seed_for(2, "B"))
         A, B = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
@@ -864,6 +894,7 @@ def bench_engine(bench, si):
     valu_cfgs = [c for c in range(ncfg) if native.mg_config_uses_mfma(0, c) == 0]
     rows = []
     for n in ENGINE_SIZES:
+        progress(f"size {n}")
         a = si.uniform((n * n,), si.seed_for(2, "A"))
         b = si.uniform((n * n,), si.seed_for(2, "B"))
         c0 = si.uniform((n * n,), si.seed_for(2, "C"))
@@ -956,11 +987,12 @@ def bench_types(bench, si):
     cases = {"fp16": fp16, "int8_end_to_end": i8_full, "int8_gemm_only": i8_gemm}
     per = {c: [] for c in cases}
     clk = {c: [] for c in cases}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for c in bench.shuffled(cases):
             r = bench.case(cases[c])
             per[c] += r["per_ms"]
-            clk[c].append(r["sclk_mhz"])
+            clk[c].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     I, J = si.sample_indices(n, n, 512, 306)
     Cf = torch.zeros(n * n, device=dev)
     bench.gemm_call("fp16", "N", "N", n, n, n, 1.0, A, n, B, n, 0.0, Cf, n, ws=fp16.workspace)()
@@ -1020,13 +1052,14 @@ def bench_smallk(bench, si):
     cases = [(p, mode) for p in runs for mode in ("warm", "flushed")]
     per = {c: [] for c in cases}
     clk = {c: [] for c in cases}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for case in bench.shuffled(cases):
             p, mode = case
             run = runs[p]
             bench.warm(run, args.warmup)
             if mode == "warm":
-                t, _ = bench.steps(run, args.steps)
+                t, _, _ = bench.steps(run, args.steps)
             else:
                 t = bench.per_launch(run, args.steps, between=lambda: flush_buf.fill_(1.0))
             per[case] += t
@@ -1098,11 +1131,12 @@ def bench_syr2k(bench, si):
     cases = {"syr2k": syr2k_fn(-1, C), "syr2k_unsplit": syr2k_fn(1, C), "two_full_gemms": two_gemms}
     per = {c: [] for c in cases}
     clk = {c: [] for c in cases}
-    for _ in range(args.rounds):
+    for rnd in range(args.rounds):
+        progress(f"round {rnd + 1}/{args.rounds}")
         for c in bench.shuffled(cases):
             r = bench.case(cases[c], steps=args.steps if c != "two_full_gemms" else max(2, args.steps // 2))
             per[c] += r["per_ms"]
-            clk[c].append(r["sclk_mhz"])
+            clk[c].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     Cf = C0.clone()
     syr2k_fn(-1, Cf)()
     I, J = si.sample_indices(n, n, 2 * SAMPLES, 308)
