@@ -115,7 +115,7 @@ int mg_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  *     if missing or too small);
  *   - MG_PATH_BF16 / MG_PATH_FP16 with M, N >= 512 and K <= 2^21: the
  *     operands rounded to bf16 / binary16 once (padded to 256 rows and 128 k);
- *   - MG_PATH_BF16X3 with configuration 6 (chosen for 256 x 256 tiles when
+ *   - MG_PATH_BF16X3 with configuration 6 or 7 (6 chosen for 256 x 256 tiles when
  *     M N >= 1250 (M + N)), M, N >= 512 and K <= 2^21: the operands split
  *     once into hi and lo bf16 terms, stored interleaved per 32 k (4 bytes
  *     per element);
@@ -285,12 +285,20 @@ int mg_force_splits(int path, int splits);
 int mg_split_count(int path, int64_t M, int64_t N, int64_t K);
 
 /*
- * Tuning table written by the autotuner: text lines "path mb nb kb config
- * [mode]", where mb/nb/kb are round(log2(M/N/K)) (0..20), config an id from
- * mg_config_info and mode 's' (single GEMMs, the default) or 'b' (the batched
- * kernel, which falls back to 's' entries); '#' starts a comment.  A loaded
- * table replaces the previous one; NULL clears it.  Selection order for every
- * GEMM: mg_force_config, then the table, then the built-in rule.  Load it before launching GEMMs from
+ * Tuning table written by the autotuner (the blocking decision of
+ * Section 3.1, Eq. 1-7, made by measuring the candidates that a model of the
+ * GPU's memories admits).  Text lines, '#' starts a comment:
+ *   "path mb nb kb config [mode]" with mb/nb/kb = round(log2(M/N/K)) (0..20)
+ *     and mode 's' (single GEMMs, the default) or 'b' (the batched kernel,
+ *     which falls back to 's' entries);
+ *   "path M N K config x [splits]": one exact shape (1 <= M, N, K <=
+ *     INT_MAX) of single GEMMs, with the number of K ranges to cut its K
+ *     loop into (1..16; omitted or -1: the automatic split rule).
+ * config is an id from mg_config_info.  A loaded table replaces the previous
+ * one; NULL clears it.  Selection order for every GEMM: mg_force_config,
+ * then an exact entry, then the bucket entries, then the built-in rule (an
+ * exact entry whose splits exceed 1 is skipped when the caller's workspace
+ * cannot hold the partial products).  Load it before launching GEMMs from
  * other threads.  Returns MG_ERR_BAD_TABLE (previous table kept) for an
  * unreadable or malformed file.
  */

@@ -19,9 +19,19 @@ read the table.  Two modes:
            would favour small tiles just to occupy more compute units);
   single:  candidates are all configurations of the path, timed on one GEMM.
 
+  exact:   for each given shape (default: the benchmark workloads' shapes),
+           the candidates the blocking model admits (blocking.py, the
+           Eq. 1-7 analogue: LDS, register file, L2 / Infinity Cache,
+           divisibility, rounds over the compute units) plus the library's
+           current plan, each a (configuration, K ranges) pair, timed on one
+           GEMM; the fastest becomes an exact-shape line "path M N K config x
+           splits", which single GEMMs of that shape read before any bucket.
+
 Usage (on a GPU):
     python -m paper_2305_18236_amd.autotune --mode batched --paths fp32,bf16x3,bf16 \
         --out paper_2305_18236_amd/tuning_table.txt
+    python -m paper_2305_18236_amd.autotune --mode exact --paths fp32,bf16x3,bf16,fp16,fp8,int8 \
+        --merge paper_2305_18236_amd/tuning_table.txt
 """
 from __future__ import annotations
 
@@ -31,9 +41,17 @@ import os
 import sys
 import time
 
-from . import _native
+from . import _native, blocking
 
-PATH_IDS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4}
+PATH_IDS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp8": 3, "fp16": 4, "int8": 5}
+
+# The benchmark workloads' shapes: the small case, the FP32 sweep, the shapes
+# whose workgroups do not fall into whole rounds, and the six products of the
+# differentiable chain (X 4096x2048, W1 2048x8192, W2 8192x2048).
+EXACT_SHAPES = [(256, 256, 256), (1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096),
+                (8192, 8192, 8192), (8192, 8192, 256), (256, 8192, 8192), (16384, 1024, 4096),
+                (1536, 1536, 1536), (3072, 3072, 3072), (6144, 6144, 6144), (3072, 3072, 1024),
+                (4096, 8192, 2048), (4096, 2048, 8192), (8192, 2048, 4096), (2048, 8192, 4096)]
 SLOTS = 512          # workgroup slots of the persistent kernel: 256 CUs x 2
 BATCHED_CFGS = {0: [3, 0], 1: [4, 5, 2], 2: [4, 5, 2], 4: [4, 5, 2]}
 
@@ -141,16 +159,143 @@ def tune(paths=("fp32", "bf16x3", "bf16"), mode="batched", buckets=range(5, 12),
     return text
 
 
+def _plan_now(pid, M, N, K):
+    """(config, K ranges) the library runs now for this shape with a full workspace."""
+    if pid == 5:
+        return _native.mg_tuned_config(5, M, N, K), 1
+    need = _native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
+    st, cfg, splits, _ = _native.mg_gemm_plan(pid, M, N, K, need)
+    return cfg, splits
+
+
+def tune_exact(paths, shapes=EXACT_SHAPES, reps=5, log=sys.stdout):
+    """Exact-shape lines for `shapes` on `paths` (see the module docstring)."""
+    import torch
+    dev = torch.device("cuda:0")
+    _native.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    lines = []
+    for path in paths:
+        pid = PATH_IDS[path]
+        cfgs = blocking.library_configs(_native, pid)
+        for (M, N, K) in shapes:
+            if pid == 5:
+                A = torch.randint(-128, 128, (M * K,), dtype=torch.int8, device=dev)
+                B = torch.randint(-128, 128, (K * N,), dtype=torch.int8, device=dev)
+                C = torch.zeros(M * N, dtype=torch.int32, device=dev)
+            else:
+                A = torch.rand(M * K, device=dev) * 2 - 1
+                B = torch.rand(K * N, device=dev) * 2 - 1
+                C = torch.rand(M * N, device=dev) * 2 - 1
+            default = _plan_now(pid, M, N, K)
+            cands = blocking.candidates(cfgs, M, N, K)
+            if default not in cands:
+                cands.append(default)
+            results = []
+            for cfg, splits in cands:
+                assert _native.mg_force_config(pid, cfg) == 0
+                if pid != 5:   # INT8 has no split
+                    assert _native.mg_force_splits(pid, splits) == 0
+                try:
+                    if pid == 5:
+                        need = _native.mg_gemm_i8_workspace_size(M, N, K)
+                    else:
+                        need = _native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
+                    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+                    if pid == 5:
+                        def run():
+                            _native.check(_native.mg_gemm_i8("N", "N", M, N, K, 1, A.data_ptr(), K, B.data_ptr(), N,
+                                                             0, C.data_ptr(), N, ws.data_ptr(), need, stream),
+                                          "mg_gemm_i8")
+                    else:
+                        def run():
+                            _native.check(_native.mg_gemm(pid, "N", "N", M, N, K, 1.5, A.data_ptr(), K, B.data_ptr(),
+                                                          N, 0.5, C.data_ptr(), N, ws.data_ptr(), need, stream),
+                                          "mg_gemm")
+                    ms = _time_launches(torch, run, reps)
+                finally:
+                    _native.mg_force_config(pid, -1)
+                    if pid != 5:
+                        _native.mg_force_splits(pid, -1)
+                results.append((ms, cfg, splits))
+            results.sort()
+            ms, cfg, splits = results[0]
+            dms = [r[0] for r in results if (r[1], r[2]) == default][0]
+            lines.append(f"{pid} {M} {N} {K} {cfg} x {splits}")
+            print(f"{path} {M}x{N}x{K}: config {cfg} splits {splits} {ms * 1e3:.1f} us "
+                  f"({2.0 * M * N * K / ms / 1e9:.1f} TFLOP/s); rule's plan {default} {dms * 1e3:.1f} us; "
+                  f"{len(results)} candidates", file=log, flush=True)
+            del A, B, C
+    return lines
+
+
+def _time_launches(torch, run, reps):
+    """Median time of one launch: warm up for about 30 ms, then `reps` blocks
+    of launches between HIP events (enough launches per block for ~2 ms)."""
+    t0 = time.perf_counter()
+    n = 0
+    while n < 3 or (time.perf_counter() - t0) < 0.03:
+        run()
+        n += 1
+        if n % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run()
+    e1.record()
+    torch.cuda.synchronize()
+    per = max(e0.elapsed_time(e1), 1e-3)
+    count = max(1, min(50, int(2.0 / per)))
+    out = []
+    for _ in range(reps):
+        e0.record()
+        for _ in range(count):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / count)
+    out.sort()
+    return out[len(out) // 2]
+
+
+def merge_exact(table_path, new_lines):
+    """Replace the exact-shape lines of `table_path` for the shapes in
+    new_lines (same path, M, N, K); keep every other line."""
+    keys = {tuple(l.split()[:4]) for l in new_lines}
+    kept = []
+    if os.path.exists(table_path):
+        for line in open(table_path):
+            f = line.split()
+            if len(f) >= 6 and not line.lstrip().startswith("#") and f[5] == "x" and tuple(f[:4]) in keys:
+                continue
+            kept.append(line.rstrip("\n"))
+    stamp = f"# exact-shape lines (mode x: path M N K config x splits), measured {time.strftime('%Y-%m-%d')}"
+    kept = [l for l in kept if not l.startswith("# exact-shape lines")]
+    with open(table_path, "w") as f:
+        f.write("\n".join(kept + [stamp] + list(new_lines)) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["batched", "single"], default="batched")
+    ap.add_argument("--mode", choices=["batched", "single", "exact"], default="batched")
     ap.add_argument("--paths", default="fp32,bf16x3,bf16")
     ap.add_argument("--min-bucket", type=int, default=5)
     ap.add_argument("--max-bucket", type=int, default=11)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--merge", default=None, help="exact mode: table file whose exact lines are replaced")
     a = ap.parse_args(argv)
     os.environ["MGEMM_TUNING"] = "none"   # measure the candidates, not a previous table
+    if a.mode == "exact":
+        lines = tune_exact(tuple(a.paths.split(",")), reps=max(a.reps, 5))
+        if a.merge:
+            merge_exact(a.merge, lines)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write("\n".join(lines) + "\n")
+        return
     tune(tuple(a.paths.split(",")), a.mode, range(a.min_bucket, a.max_bucket + 1), a.reps, a.out)
 
 

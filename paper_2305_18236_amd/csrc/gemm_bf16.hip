@@ -208,6 +208,11 @@ const SgemmConfig kBf16Configs[] = {
     // pre-packed planes (bf16x3: the interleaved ones); without the planes
     // it runs as configuration 1
     {6, 256, 256, 64, 128, 64},
+    // configuration 2's tiles with panels copied straight into LDS, on
+    // pre-packed planes (64 KiB of LDS: two workgroups per compute unit, so
+    // one's epilogue overlaps the other's K loop when K is short); without
+    // the planes it runs as configuration 2
+    {7, 128, 128, 64, 64, 64},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
@@ -224,6 +229,9 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 6:
         if (packed) return launch_bf16_direct<256, 256, 128, 64, TERMS>(g, stream);
         return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
+    case 7:
+        if (packed) return launch_bf16_direct<128, 128, 64, 64, TERMS>(g, stream);
+        return launch_bf16_cfg<128, 128, 32, 64, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }

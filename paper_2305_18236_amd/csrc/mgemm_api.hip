@@ -131,6 +131,27 @@ int table_lookup(int path, int64_t M, int64_t N, int64_t K, int mode = 0)
     return g_table[mode][path][bucket(M)][bucket(N)][bucket(K)];
 }
 
+// Exact-shape entries ('x' lines of the table): the configuration and the
+// number of K ranges the autotuner measured best for one (path, M, N, K).
+// They take precedence over the log2 buckets, which cannot tell apart shapes
+// such as 1536^3 and 2048^3 whose best plans differ.  Replaced as a whole by
+// mg_load_tuning; read without locking (load the table before launching
+// GEMMs from other threads).
+struct ExactEntry {
+    int path;
+    int64_t M, N, K;
+    int cfg;
+    int splits;   // K ranges (1: no split); -1: the automatic rule's
+};
+std::vector<ExactEntry> g_exact;
+
+const ExactEntry* exact_lookup(int path, int64_t M, int64_t N, int64_t K)
+{
+    for (const ExactEntry& e : g_exact)
+        if (e.path == path && e.M == M && e.N == N && e.K == K) return &e;
+    return nullptr;
+}
+
 int device_cus();
 
 // ---- Split-K: when a GEMM has fewer output tiles than the GPU has compute
@@ -389,7 +410,8 @@ bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 // FP32 ones for no gain (about 347 against 370 TFLOP/s at 8192^3).
 bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K)
 {
-    if (path == MG_PATH_BF16X3) return cfg == 6 && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+    if (path == MG_PATH_BF16X3)
+        return (cfg == 6 || cfg == 7) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
     return bf16_prepack_pays(path, M, N, K);
 }
 
@@ -427,6 +449,11 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool sp
         return p;
     const mg::SgemmConfig& c = table_of(path).cfgs[cfg];
     int s = g_forced_splits[path].load();
+    if (s < 0) {
+        // the K ranges tuned with this configuration for this exact shape
+        const ExactEntry* e = exact_lookup(path, M, N, K);
+        if (e != nullptr && e->cfg == cfg && e->splits > 0) s = e->splits;
+    }
     if (s < 0 && path == MG_PATH_FP32) {
         // the K ranges the round plan chose with this configuration
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
@@ -502,12 +529,17 @@ int run_fp8_pack(bool trans, int64_t R, int64_t K, const float* X, int64_t ldx, 
     return hip_status(mg::launch_fp8_pack(trans, X, ldx, R, K, vec, q, Kp, sc, Kp / 128, Rp, Kp, stream));
 }
 
-// forced > tuned > default rule.  split_ok: whether a K split may be planned
-// (false when the caller's workspace cannot hold the partial products).
+// forced > tuned for this exact shape > tuned for its bucket > default
+// rule.  split_ok: whether a K split may be planned (false when the caller's
+// workspace cannot hold the partial products); an exact entry tuned with a
+// split does not apply then, since its tile was chosen for split K loops.
 int pick_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
 {
     int cfg = g_forced[path].load();
     if (cfg >= 0) return cfg;
+    std::call_once(g_table_init, table_clear);
+    const ExactEntry* e = exact_lookup(path, M, N, K);
+    if (e != nullptr && (split_ok || e->splits <= 1)) return e->cfg;
     cfg = table_lookup(path, M, N, K);
     if (config_valid(path, cfg)) return cfg;
     return choose_config(path, M, N, K, split_ok);
@@ -1118,32 +1150,58 @@ int mg_load_tuning(const char* path)
     std::lock_guard<std::mutex> lock(g_table_mutex);
     if (path == nullptr) {
         table_clear();
+        g_exact.clear();
         return MG_OK;
     }
     FILE* f = std::fopen(path, "r");
     if (!f) return MG_ERR_BAD_TABLE;
     static int8_t fresh[2][kPaths][kBuckets][kBuckets][kBuckets];
     std::memset(fresh, -1, sizeof(fresh));
+    std::vector<ExactEntry> exact;
     char line[256];
     int bad = 0;
     while (std::fgets(line, sizeof(line), f)) {
         const char* q = line;
         while (*q == ' ' || *q == '\t') ++q;
         if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
-        int p, mb, nb, kb, cfg;
+        long long p, a, b, c, cfg, splits = -1;
         char mode[8] = "s";
-        const int got = std::sscanf(q, "%d %d %d %d %d %7s", &p, &mb, &nb, &kb, &cfg, mode);
-        if (got < 5 || !valid_path(p) || mb < 0 || mb >= kBuckets || nb < 0 || nb >= kBuckets || kb < 0 ||
-            kb >= kBuckets || !config_valid(p, cfg) || !(mode[0] == 's' || mode[0] == 'b') ||
+        int used = 0;
+        const int got = std::sscanf(q, "%lld %lld %lld %lld %lld %7s %n", &p, &a, &b, &c, &cfg, mode, &used);
+        if (got < 5 || p < 0 || p >= kPaths || cfg < 0 || cfg > 127 || !config_valid(int(p), int(cfg)) ||
             mode[1] != 0) {
             bad = 1;
             break;
         }
-        fresh[mode[0] == 'b' ? 1 : 0][p][mb][nb][kb] = int8_t(cfg);
+        if (mode[0] == 'x') {
+            // exact shape: M N K (1 .. INT_MAX) and an optional K-range count
+            if (got == 6 && q[used] != 0 && q[used] != '\n' && q[used] != '\r' && q[used] != '#') {
+                char* end = nullptr;
+                splits = std::strtoll(q + used, &end, 10);
+                if (end == q + used) {
+                    bad = 1;
+                    break;
+                }
+            }
+            if (a < 1 || b < 1 || c < 1 || a > INT_MAX || b > INT_MAX || c > INT_MAX ||
+                !(splits == -1 || (splits >= 1 && splits <= kMaxSplits))) {
+                bad = 1;
+                break;
+            }
+            exact.push_back(ExactEntry{int(p), a, b, c, int(cfg), int(splits)});
+            continue;
+        }
+        if (!(mode[0] == 's' || mode[0] == 'b') || a < 0 || a >= kBuckets || b < 0 || b >= kBuckets || c < 0 ||
+            c >= kBuckets) {
+            bad = 1;
+            break;
+        }
+        fresh[mode[0] == 'b' ? 1 : 0][p][a][b][c] = int8_t(cfg);
     }
     std::fclose(f);
     if (bad) return MG_ERR_BAD_TABLE;
     std::memcpy(g_table, fresh, sizeof(g_table));
+    g_exact.swap(exact);
     return MG_OK;
 }
 

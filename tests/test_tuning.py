@@ -269,3 +269,62 @@ def test_plan_argument_errors(native):
     need = native.mg_gemm_workspace_size(3, "N", "N", 512, 512, 512)
     assert native.mg_gemm_plan(3, 512, 512, 512, need)[0] == 0
     assert native.mg_gemm_plan(3, 512, 512, 512, need - 1)[0] == -100
+
+
+def test_exact_entries_precede_buckets_and_carry_splits(native, tmp_path):
+    """An exact-shape line steers that shape only, ahead of the bucket line of
+    its bucket; its K-range count becomes the plan's; a forced configuration
+    still wins; without room for the partials a split entry is skipped."""
+    p = tmp_path / "t.txt"
+    # 1536^3 and 2048^3 share bucket 11
+    p.write_text("0 11 11 11 3\n0 1536 1536 1536 0 x 3\n1 2048 2048 2048 2 x\n")
+    assert native.mg_load_tuning(str(p)) == 0
+    assert native.mg_tuned_config(0, 1536, 1536, 1536) == 0
+    assert native.mg_tuned_config(0, 2048, 2048, 2048) == 3          # the bucket entry
+    assert native.mg_split_count(0, 1536, 1536, 1536) == 3
+    full = native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 1536)
+    assert native.mg_gemm_plan(0, 1536, 1536, 1536, full) == (0, 0, 3, 0)
+    st, cfg, splits, _ = native.mg_gemm_plan(0, 1536, 1536, 1536, 0)
+    assert st == 0 and splits == 1 and cfg == 3                       # falls back to the bucket entry
+    # no split count given: the automatic split rule for that configuration
+    assert native.mg_tuned_config(1, 2048, 2048, 2048) == 2
+    assert native.mg_force_config(0, 5) == 0
+    try:
+        assert native.mg_tuned_config(0, 1536, 1536, 1536) == 5
+    finally:
+        native.mg_force_config(0, -1)
+    # clearing the table drops exact entries too
+    native.mg_load_tuning(None)
+    assert native.mg_tuned_config(0, 1536, 1536, 1536) != 0 or native.mg_split_count(0, 1536, 1536, 1536) != 3
+
+
+@pytest.mark.parametrize("text", ["0 0 8 8 3 x\n", "0 8 8 8 3 x 17\n", "0 8 8 8 3 x 0\n", "0 8 8 8 3 x z\n",
+                                  "0 8 8 8 99 x 2\n", "0 3000000000 8 8 3 x 1\n", "9 8 8 8 3 x 1\n"])
+def test_malformed_exact_entries_rejected(native, tmp_path, text):
+    good = tmp_path / "good.txt"
+    good.write_text("0 100 100 100 3 x 1\n")
+    assert native.mg_load_tuning(str(good)) == 0
+    bad = tmp_path / "bad.txt"
+    bad.write_text(text)
+    assert native.mg_load_tuning(str(bad)) == -103
+    assert native.mg_tuned_config(0, 100, 100, 100) == 3
+
+
+def test_committed_table_parses_and_its_exact_entries_are_admissible(native):
+    """Every exact line of the committed table loads, names a configuration
+    the blocking model admits for its shape, and a K-range count the library
+    can cut K into."""
+    from paper_2305_18236_amd import blocking
+    path = os.path.join(os.path.dirname(autotune.__file__), "tuning_table.txt")
+    assert native.mg_load_tuning(path) == 0
+    for line in open(path):
+        f = line.split()
+        if line.startswith("#") or len(f) < 6 or f[5] != "x":
+            continue
+        pid, M, N, K, cfg = (int(v) for v in f[:5])
+        splits = int(f[6]) if len(f) > 6 else -1
+        cfgs = {c.id: c for c in blocking.library_configs(native, pid)}
+        assert not blocking.feasible(cfgs[cfg]), line
+        assert native.mg_tuned_config(pid, M, N, K) == cfg, line
+        if splits > 1:
+            assert blocking.effective_splits(K, splits) == splits, line
