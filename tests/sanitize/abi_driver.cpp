@@ -83,7 +83,15 @@ int main()
     CHECK(mg_load_tuning(write_table("bad2", "0 99 5 5 1\n").c_str()) == MG_ERR_BAD_TABLE);
     CHECK(mg_load_tuning(write_table("bad3", "0 5 5 5 999\n").c_str()) == MG_ERR_BAD_TABLE);
     CHECK(mg_load_tuning(write_table("bad4", "7 5 5 5 1 s\n").c_str()) == MG_ERR_BAD_TABLE);
-    CHECK(mg_load_tuning(write_table("bad5", "0 5 5 5 1 x\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("bad5", "0 5 5 5 1 q\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("bad9", "0 0 5 5 1 x\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("bad10", "0 5 5 5 1 x 17\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("bad11", "0 9999999999 5 5 1 x 2\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("bad12", "0 5 5 5 1 x y\n").c_str()) == MG_ERR_BAD_TABLE);
+    CHECK(mg_load_tuning(write_table("exact", "0 1536 1536 1536 0 x 3\n0 11 11 11 3\n").c_str()) == MG_OK);
+    CHECK(mg_tuned_config(0, 1536, 1536, 1536) == 0);
+    CHECK(mg_tuned_config(0, 2048, 2048, 2048) == 3);
+    CHECK(mg_split_count(0, 1536, 1536, 1536) == 3);
     CHECK(mg_load_tuning(write_table("bad6", "0 -1 5 5 1\n").c_str()) == MG_ERR_BAD_TABLE);
     std::string longline(100000, '7');
     CHECK(mg_load_tuning(write_table("bad8", (longline + "\n").c_str()) .c_str()) == MG_ERR_BAD_TABLE);
