@@ -18,6 +18,14 @@ def native():
     _native._load_default_tuning(_native.lib())
 
 
+@pytest.fixture()
+def rule(native):
+    """The library with no tuning table: the built-in rule alone decides
+    (the native fixture restores the committed table afterwards)."""
+    native.mg_load_tuning(None)
+    return native
+
+
 def test_bucket_rule_matches_library(native, tmp_path):
     # a table that maps every (mb, nb, kb) of path 0 to a config derived from mb
     n = native.mg_num_configs(0)
@@ -130,7 +138,8 @@ def test_problem_struct_layout(native):
     assert ctypes.sizeof(native.mg_problem) == 8 + 24 + 8 + 48
 
 
-def test_split_plan_rules(native):
+def test_split_plan_rules(rule):
+    native = rule
     """Host-side split-K plan: ranges are multiples of 128 deep, K < 256 never
     splits, forcing is validated, and the workspace covers the partials."""
     try:
@@ -156,7 +165,8 @@ def test_split_plan_rules(native):
     assert 2 <= s <= 16 and 4096 / s >= 256 - 128
 
 
-def test_sixteen_bit_direct_copy_choice(native):
+def test_sixteen_bit_direct_copy_choice(rule):
+    native = rule
     """16-bit problems large enough for pre-packed planes and for 256 x 256
     tiles take configuration 6 (the same tiles, panels copied straight into
     LDS); problems too small to pre-pack, or beyond the planes' K limit,
@@ -180,7 +190,8 @@ def test_sixteen_bit_direct_copy_choice(native):
     assert native.mg_gemm_workspace_size(1, "N", "N", 256, 8192, 8192) > 0   # split-K partials only
 
 
-def test_fp32_round_plan(native):
+def test_fp32_round_plan(rule):
+    native = rule
     """Where the tile ladder's workgroups leave the last round on the compute
     units mostly empty, the FP32 rule re-plans tile and K ranges (3072^3:
     288 workgroups of 256 x 256 on 256 compute units before); shapes whose
@@ -201,7 +212,8 @@ def test_fp32_round_plan(native):
     assert native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 4096) == 4 * 1536 * 1536 * 4
 
 
-def test_sixteen_bit_split_rule(native):
+def test_sixteen_bit_split_rule(rule):
+    native = rule
     """16-bit paths split K into as many ranges as fit one round of
     workgroups (rounded down)."""
     for path in (1, 2, 4):
@@ -214,7 +226,8 @@ def test_sixteen_bit_split_rule(native):
         assert native.mg_split_count(path, 4096, 2048, 8192) == 2     # 128 tiles: 256 workgroups
 
 
-def test_fp8_big_tile_threshold(native):
+def test_fp8_big_tile_threshold(rule):
+    native = rule
     """FP8 takes the 256 x 256 direct-copy tile once its tiles keep more than
     half the compute units busy (FP8 never splits K)."""
     assert native.mg_tuned_config(3, 3072, 3072, 3072) == 7     # 144 tiles
@@ -224,7 +237,8 @@ def test_fp8_big_tile_threshold(native):
     assert native.mg_tuned_config(5, 4096, 2048, 8192) == 4     # INT8, 128 tiles
 
 
-def test_plan_without_workspace_is_chosen_for_an_unsplit_k_loop(native):
+def test_plan_without_workspace_is_chosen_for_an_unsplit_k_loop(rule):
+    native = rule
     """mg_sgemm passes no workspace.  Its tile must be the best one for an
     unsplit K loop, not the split plan's tile run unsplit: at 6144^3 the split
     plan takes 256 x 256 tiles in four K ranges, while unsplit 128 x 128
@@ -328,3 +342,32 @@ def test_committed_table_parses_and_its_exact_entries_are_admissible(native):
         assert native.mg_tuned_config(pid, M, N, K) == cfg, line
         if splits > 1:
             assert blocking.effective_splits(K, splits) == splits, line
+
+
+def test_committed_table_drives_the_tuned_shapes(native):
+    """The committed exact entries are what single GEMMs of those shapes run,
+    and for some of them that differs from the built-in rule (measured
+    faster): e.g. BF16 at 1024^3 runs 64 x 64 tiles unsplit, where the rule
+    would take 128 x 128 tiles in four K ranges."""
+    path = os.path.join(os.path.dirname(autotune.__file__), "tuning_table.txt")
+    entries = []
+    for line in open(path):
+        f = line.split()
+        if not line.startswith("#") and len(f) >= 7 and f[5] == "x":
+            entries.append(tuple(int(v) for v in f[:5]) + (int(f[6]),))
+    assert len(entries) >= 90
+    differ = 0
+    for pid, M, N, K, cfg, splits in entries:
+        full = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K) if pid != 5 else 0
+        if pid != 5:
+            st, c, s, _ = native.mg_gemm_plan(pid, M, N, K, full)
+            assert (st, c, s) == (0, cfg, splits), (pid, M, N, K)
+    native.mg_load_tuning(None)
+    for pid, M, N, K, cfg, splits in entries:
+        if pid == 5:
+            continue
+        full = native.mg_gemm_workspace_size(pid, "N", "N", M, N, K)
+        st, c, s, _ = native.mg_gemm_plan(pid, M, N, K, full)
+        differ += (c, s) != (cfg, splits)
+    assert differ >= 5
+    assert (2, 1024, 1024, 1024, 4, 1) in entries
