@@ -629,8 +629,8 @@ def bench_mixed(bench, si):
 def bench_batched(bench, si):
     """512 GEMMs with M, N, K log-uniform in [32, 2048] (multiples of 8),
     U[-1, 1], alpha 1, beta 0: one persistent launch, against one launch per
-    problem (summed device time of the 512 kernels, each bracketed by HIP
-    events, and the wall time of the host loop that issues them)."""
+    problem (the device time of the 512 launches replayed from one HIP graph,
+    and the wall time of the host loop that issues them one by one)."""
     torch, native, dev, args = bench.torch, bench.native, bench.dev, bench.args
     sp = bench.sp
     sizes = si.batched_sizes(512, si.seed_for(4, "A"))
@@ -694,26 +694,15 @@ def bench_batched(bench, si):
             per[case] += r["per_ms"]
             clk[case].append([r["sclk_mhz_during"], r["sclk_mhz"]])
     for path in ("fp32", "bf16x3"):
-        # device time of one launch per problem: each launch between its own events
-        fns = [one(path, i) for i in range(len(ops))]
-        bench.warm(loop(path), 1)
-        dev_ms = []
-        for _ in range(max(3, args.rounds)):
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fns]
-            for f, (e0, e1) in zip(fns, ev):
-                e0.record(bench.stream)
-                f()
-                e1.record(bench.stream)
-            torch.cuda.synchronize()
-            dev_ms.append(sum(e0.elapsed_time(e1) for e0, e1 in ev))
+        dms, graph_ok = _per_problem_graph(bench, path, ops, one)
         pms = float(np.mean(per[(path, "persistent")]))
         lms = float(np.mean(per[(path, "host_loop")]))
-        dms = float(np.median(dev_ms))
         res = {"persistent": {"ms": round(pms, 4), "tflops": round(tflops(flops, pms), 2), "launches": 1,
                               "step_ms": stats(per[(path, "persistent")]), "sclk_mhz": clk[(path, "persistent")]},
                "per_problem_device": {"ms": round(dms, 4), "tflops": round(tflops(flops, dms), 2),
-                                      "launches": len(ops),
-                                      "how": "sum of the 512 calls' own event-bracketed device times"},
+                                      "launches": len(ops), "replays_match_eager": graph_ok,
+                                      "how": "the 512 single-GEMM launches captured in one HIP graph and "
+                                             "replayed (device time without the host's per-call overhead)"},
                "per_problem_host_loop": {"ms": round(lms, 4), "tflops": round(tflops(flops, lms), 2),
                                          "launches": len(ops), "step_ms": stats(per[(path, "host_loop")])},
                "speedup_vs_per_problem_device": round(dms / pms, 3),
@@ -737,6 +726,45 @@ def bench_batched(bench, si):
     out["ms_per_step"] = out["paths"]["fp32"]["persistent"]["ms"]
     out["bf16x3_vs_fp32_persistent"] = round(out["paths"]["bf16x3"]["persistent"]["tflops"] / out["value"], 3)
     return out
+
+
+def _per_problem_graph(bench, path, ops, one):
+    """Median time of one replay of a HIP graph holding the 512 per-problem
+    mg_gemm launches (their workspaces allocated before capture), and whether
+    every replay reproduced the eager launches' outputs bit for bit."""
+    torch, native = bench.torch, bench.native
+    runs = [one(path, i) for i in range(len(ops))]          # allocates the workspaces
+    for r in runs:
+        r()
+    torch.cuda.synchronize()
+    eager = [C.clone() for _, _, C in ops]
+    pid = PATH_ID[path]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cs = torch.cuda.current_stream().cuda_stream
+        for (A, B, C), r in zip(ops, runs):
+            m, k = A.shape
+            n = B.shape[1]
+            ws = r.workspace
+            need = native.mg_gemm_workspace_size(pid, "N", "N", m, n, k)
+            native.check(native.mg_gemm(pid, "N", "N", m, n, k, 1.0, A.data_ptr(), k, B.data_ptr(), n, 0.0,
+                                        C.data_ptr(), n, ws.data_ptr(), need, cs), "mg_gemm (capture)")
+    ok = True
+    times = []
+    for rep in range(6):
+        for _, _, C in ops:
+            C.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bench.stream)
+        g.replay()
+        e1.record(bench.stream)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(e0.elapsed_time(e1))
+        ok = ok and all(torch.equal(C, E) for (_, _, C), E in zip(ops, eager))
+    del g
+    return float(np.median(times)), ok
 
 
 def _batched_tail(bench, pid, arr, count, ws, need):
