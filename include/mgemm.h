@@ -285,6 +285,17 @@ int mg_force_splits(int path, int splits);
 int mg_split_count(int path, int64_t M, int64_t N, int64_t K);
 
 /*
+ * Force the order in which the single-GEMM kernels of `path` (also
+ * MG_CONFIGS_I8) walk their output tiles: groups of group_m (1..64) tile rows
+ * taken column by column; remap 1 first gives each of the 8 XCDs a
+ * contiguous range of that raster, remap 0 leaves the hardware's round-robin
+ * placement (XCD = workgroup id mod 8).  remap -1 returns to the automatic
+ * choice (group_m ignored).  Process-wide; meant for the autotuner and
+ * tests.  The order changes only where each tile runs, never a result bit.
+ */
+int mg_force_tile_order(int path, int remap, int group_m);
+
+/*
  * Tuning table written by the autotuner (the blocking decision of
  * Section 3.1, Eq. 1-7, made by measuring the candidates that a model of the
  * GPU's memories admits).  Text lines, '#' starts a comment:

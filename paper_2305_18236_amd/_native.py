@@ -71,6 +71,8 @@ def lib():
     L.mg_config_packs.restype = ci
     L.mg_force_splits.argtypes = [ci, ci]
     L.mg_force_splits.restype = ci
+    L.mg_force_tile_order.argtypes = [ci, ci, ci]
+    L.mg_force_tile_order.restype = ci
     L.mg_split_count.argtypes = [ci, i64, i64, i64]
     L.mg_split_count.restype = ci
     L.mg_gemm_plan.argtypes = [ci, i64, i64, i64, ctypes.c_size_t, ctypes.POINTER(ci)]
@@ -291,6 +293,10 @@ def mg_config_uses_mfma(path, index) -> int:
 
 def mg_force_splits(path, splits) -> int:
     return int(lib().mg_force_splits(int(path), int(splits)))
+
+
+def mg_force_tile_order(path, remap, group_m=4) -> int:
+    return int(lib().mg_force_tile_order(int(path), int(remap), int(group_m)))
 
 
 def mg_split_count(path, M, N, K) -> int:

@@ -25,6 +25,7 @@ struct GemmArgs {
     float alpha, beta;
     int tiles_m, tiles_n;
     int group_m;      // tile rows per raster group (L2 reuse of B panels)
+    int remap;        // 1: give each XCD a contiguous range of tiles (see tile_of)
     // vec_a / vec_b: 16-byte loads allowed (16-byte aligned, ld % 4 == 0) and
     // in-panel byte offsets fit 32 bits (ld < 2^22 - 64), which lets interior
     // panels address through a uniform base plus a 32-bit per-lane offset.
@@ -74,21 +75,22 @@ struct Fp8Args {
     int64_t M, N, Kp;
     int64_t ldq, lds, ldc;
     float alpha, beta;
-    int tiles_m, tiles_n, group_m;
+    int tiles_m, tiles_n, group_m, remap;
 };
 
-// Map a linear workgroup id to an output tile (tm, tn).
+// Map a linear workgroup id to an output tile (tm, tn): a raster that walks
+// groups of `group_m` tile rows column by column, so that tiles running at
+// the same time share A row panels and B column panels.
 //
-// Hardware hands consecutive workgroup ids to the 8 XCDs round-robin.  We
-// first undo that, so that each XCD owns a contiguous range of logical ids,
-// then walk that range in groups of `group_m` tile rows, column by column,
-// so that workgroups resident on one XCD at the same time share A row panels
-// and B column panels in that XCD's L2.
-MG_DEVICE void tile_of(int pid, int tiles_m, int tiles_n, int group_m, int& tm, int& tn)
+// Hardware hands consecutive workgroup ids to the 8 XCDs round-robin.  With
+// `remap` set the ids are first permuted so that each XCD owns a contiguous
+// range of the raster (its resident tiles then form one compact block per
+// XCD); without it each XCD takes every eighth tile of the raster.
+MG_DEVICE void tile_of(int pid, int tiles_m, int tiles_n, int group_m, int remap, int& tm, int& tn)
 {
     const int total = tiles_m * tiles_n;
     constexpr int XCDS = 8;
-    if (total % XCDS == 0) {
+    if (remap && total % XCDS == 0) {
         const int per = total / XCDS;
         pid = (pid % XCDS) * per + pid / XCDS;
     }

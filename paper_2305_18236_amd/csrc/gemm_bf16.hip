@@ -14,7 +14,7 @@ void gemm_bf16_kernel(GemmArgs args)
     GemmArgs g = args;
     split_k_view<TA, TB, false>(g);
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     bf16_tile<BM, BN, BK, WM, WN, TA, TB, TERMS>(g, tm, tn, smem);
 }
 
@@ -28,7 +28,7 @@ void gemm_bf16_packed_kernel(GemmArgs args)
     GemmArgs g = args;
     split_k_view<false, true, true>(g);
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     bf16_tile<BM, BN, BK, WM, WN, false, true, TERMS, true>(g, tm, tn, smem);
 }
 
@@ -79,7 +79,7 @@ void gemm_bf16_direct_kernel(GemmArgs args)
     const int c = lane & 31, h = lane >> 5;
 
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
     const uint8_t* __restrict__ qa =
         reinterpret_cast<const uint8_t*>(reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda) + kbyte0;

@@ -13,7 +13,7 @@ void sgemm_direct_kernel(GemmArgs args)
     GemmArgs g = args;
     split_k_view<TA, TB, false>(g);
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     direct_tile<WAVES_M, WAVES_N, WM, WN, TA, TB>(g, tm, tn);
 }
 

@@ -13,7 +13,7 @@ void sgemm_mfma_kernel(GemmArgs args)
     GemmArgs g = args;
     split_k_view<TA, TB, false>(g);
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     sgemm_tile<BM, BN, BK, WM, WN, TA, TB>(g, tm, tn, smem);
 }
 

@@ -186,7 +186,7 @@ void gemm_fp8_kernel(Fp8Args g)
     const int c = lane & 31, h = lane >> 5;
 
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
     using PA = BytePanel<BM, NT, LDR>;
@@ -383,7 +383,7 @@ void gemm_fp8_direct_kernel(Fp8Args g)
     const int c = lane & 31, h = lane >> 5;
 
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
     floatx16 acc[V][H];

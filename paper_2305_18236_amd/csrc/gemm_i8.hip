@@ -150,7 +150,7 @@ void gemm_i8_kernel(I8Args g)
     const int c = lane & 31, h = lane >> 5;
 
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
     const uint8_t* qA = reinterpret_cast<const uint8_t*>(g.qA);
     const uint8_t* qB = reinterpret_cast<const uint8_t*>(g.qB);
@@ -302,7 +302,7 @@ void gemm_i8_direct_kernel(I8Args g)
     const int c = lane & 31, h = lane >> 5;
 
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
     const uint8_t* __restrict__ qa = reinterpret_cast<const uint8_t*>(g.qA) + m0 * g.ldq;
     const uint8_t* __restrict__ qb = reinterpret_cast<const uint8_t*>(g.qB) + n0 * g.ldq;

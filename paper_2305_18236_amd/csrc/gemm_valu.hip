@@ -13,7 +13,7 @@ __global__ __launch_bounds__(256) void sgemm_valu_kernel(GemmArgs args)
     GemmArgs g = args;
     split_k_view<TA, TB, false>(g);
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, tm, tn);
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
     valu_tile<BK, TA, TB>(g, tm, tn, smem);
 }
 

@@ -93,7 +93,7 @@ struct I8Args {
     int64_t M, N, Kp;
     int64_t ldq, ldc;
     int32_t alpha, beta;
-    int tiles_m, tiles_n, group_m;
+    int tiles_m, tiles_n, group_m, remap;
 };
 extern const SgemmConfig kI8Configs[];
 extern const int kNumI8Configs;

@@ -23,6 +23,21 @@ bool is_t(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 constexpr int kPaths = 6;
 std::atomic<int> g_forced[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 std::atomic<int> g_forced_splits[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+// Forced tile order: -1 automatic, else remap * 256 + group_m.
+std::atomic<int> g_forced_order[kPaths] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+
+// The raster of the single-GEMM kernels (tile_of): group_m tile rows per
+// group, and whether each XCD gets a contiguous range of it.
+struct TileOrder {
+    int group_m, remap;
+};
+
+TileOrder tile_order(int path)
+{
+    const int f = g_forced_order[path].load();
+    if (f >= 0) return {f & 255, f >> 8};
+    return {4, 1};
+}
 
 bool valid_path(int path) { return path >= 0 && path < kPaths; }
 
@@ -503,7 +518,9 @@ int run_i8_packed(int64_t M, int64_t N, int64_t K, int32_t alpha, const int8_t* 
     g.M = M; g.N = N; g.Kp = fp8_kp(K);
     g.ldq = g.Kp; g.ldc = ldc;
     g.alpha = alpha; g.beta = beta;
-    g.group_m = 4;
+    const TileOrder o = tile_order(MG_CONFIGS_I8);
+    g.group_m = o.group_m;
+    g.remap = o.remap;
     return hip_status(mg::launch_gemm_i8(cfg, g, stream));
 }
 
@@ -517,7 +534,9 @@ int run_fp8_packed(int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* 
     g.M = M; g.N = N; g.Kp = fp8_kp(K);
     g.ldq = g.Kp; g.lds = g.Kp / 128; g.ldc = ldc;
     g.alpha = alpha; g.beta = beta;
-    g.group_m = 4;
+    const TileOrder o = tile_order(MG_PATH_FP8_T128);
+    g.group_m = o.group_m;
+    g.remap = o.remap;
     return hip_status(mg::launch_gemm_fp8(cfg, g, stream));
 }
 
@@ -590,7 +609,9 @@ int run_gemm(int path, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     g.M = M; g.N = N; g.K = K;
     g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.alpha = alpha; g.beta = beta;
-    g.group_m = 4;
+    const TileOrder o = tile_order(path);
+    g.group_m = o.group_m;
+    g.remap = o.remap;
     g.vec_a = fast_operand(A, lda);
     g.vec_b = fast_operand(B, ldb);
     g.vec_c = aligned16(C) && ldc % 4 == 0;
@@ -1126,6 +1147,18 @@ int mg_force_splits(int path, int splits)
     if (!valid_path(path)) return MG_ERR_UNSUPPORTED;
     if (splits < -1 || splits == 0 || splits > kMaxSplits) return MG_ERR_UNSUPPORTED;
     g_forced_splits[path].store(splits);
+    return MG_OK;
+}
+
+int mg_force_tile_order(int path, int remap, int group_m)
+{
+    if (!valid_path(path)) return MG_ERR_UNSUPPORTED;
+    if (remap == -1) {
+        g_forced_order[path].store(-1);
+        return MG_OK;
+    }
+    if ((remap != 0 && remap != 1) || group_m < 1 || group_m > 64) return MG_ERR_UNSUPPORTED;
+    g_forced_order[path].store(remap * 256 + group_m);
     return MG_OK;
 }
 

@@ -128,13 +128,13 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + 7 * N + 13 * K), gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     _check(Problem(530, 390, 300, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, cfg=cfg)
 
 
-@pytest.mark.parametrize("cfg", [5, 6, 7, 8])
+@pytest.mark.parametrize("cfg", [5, 6, 7, 8, 9])
 @pytest.mark.parametrize("K", [1, 128, 129, 256, 384, 1000])
 def test_interleaved_pack_panel_counts(gpu, cfg, K):
     """The two-buffer loops (interleaved staging, direct copies) and their

@@ -138,6 +138,23 @@ def test_problem_struct_layout(native):
     assert ctypes.sizeof(native.mg_problem) == 8 + 24 + 8 + 48
 
 
+def test_force_tile_order_validation(native):
+    """The tile-order override takes remap 0/1 with group_m 1..64 on the six
+    configuration tables, and -1 (any group) returns to the automatic order."""
+    try:
+        for path in range(6):
+            assert native.mg_force_tile_order(path, 0, 1) == 0
+            assert native.mg_force_tile_order(path, 1, 64) == 0
+            assert native.mg_force_tile_order(path, -1, 0) == 0
+        for remap, gm in ((2, 4), (-2, 4), (0, 0), (1, 65), (0, -3)):
+            assert native.mg_force_tile_order(0, remap, gm) == -101
+        assert native.mg_force_tile_order(6, 0, 4) == -101
+        assert native.mg_force_tile_order(-1, 0, 4) == -101
+    finally:
+        for path in range(6):
+            native.mg_force_tile_order(path, -1)
+
+
 def test_split_plan_rules(rule):
     native = rule
     """Host-side split-K plan: ranges are multiples of 128 deep, K < 256 never
