@@ -203,13 +203,24 @@ class Bench:
         torch.cuda.synchronize()
         return [a.elapsed_time(b) for a, b in out]
 
+    def load_clock(self, fn, per_ms):
+        """The clock while fn's kernels run: untimed calls (about 3 ms of
+        them) queued after the timed steps, probed from the side stream (see
+        steps); None if they finished before the probe returned."""
+        n = max(3, min(400, int(3.0 / max(float(np.median(per_ms)), 1e-3))))
+        _, _, during = self.steps(fn, n, probe=True)
+        return during
+
     def case(self, fn, steps=None, warmup=None):
-        """Warm up, time `steps` calls, then read the clock."""
+        """Warm up, time `steps` calls, read the clock right after them, then
+        the clock under the same load (outside the timed steps, so that the
+        probe's workgroups never share the GPU with a timed step)."""
         steps = self.args.steps if steps is None else steps
         warmup = self.args.warmup if warmup is None else warmup
         self.warm(fn, warmup)
-        per, total, during = self.steps(fn, steps, probe=True)
-        return {"per_ms": per, "total_ms": total, "sclk_mhz": self.sclk(), "sclk_mhz_during": during}
+        per, total, _ = self.steps(fn, steps)
+        after = self.sclk()
+        return {"per_ms": per, "total_ms": total, "sclk_mhz": after, "sclk_mhz_during": self.load_clock(fn, per)}
 
     def gemm_call(self, path, tA, tB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws=None):
         """A closure launching mg_gemm with its full workspace (allocated here once)."""
