@@ -5,7 +5,7 @@
 
 namespace mg {
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool DEEP>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
 void sgemm_mfma_kernel(GemmArgs args)
 {
@@ -14,23 +14,23 @@ void sgemm_mfma_kernel(GemmArgs args)
     split_k_view<TA, TB, false>(g);
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
-    sgemm_tile<BM, BN, BK, WM, WN, TA, TB>(g, tm, tn, smem);
+    sgemm_tile<BM, BN, BK, WM, WN, TA, TB, false, 0, DEEP>(g, tm, tn, smem);
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers, one per tile configuration.
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool DEEP = false>
 static hipError_t launch_sgemm_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stream)
 {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
     const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
-    if (!ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, false>), grid, block, 0, stream, g);
-    else if (!ta && tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, true>), grid, block, 0, stream, g);
-    else if (ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, false>), grid, block, 0, stream, g);
-    else hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, true>), grid, block, 0, stream, g);
+    if (!ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, false, DEEP>), grid, block, 0, stream, g);
+    else if (!ta && tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, true, DEEP>), grid, block, 0, stream, g);
+    else if (ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, false, DEEP>), grid, block, 0, stream, g);
+    else hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, true, DEEP>), grid, block, 0, stream, g);
     return hipGetLastError();
 }
 
@@ -52,6 +52,11 @@ const SgemmConfig kSgemmConfigs[] = {
     // thread with scalar FP32 FMAs; WM x WN is one wave's share of the tile
     {10, 128, 128, 8, 32, 128, 0, 1},
     {11, 128, 128, 16, 32, 128, 0, 1},
+    // as 3, 4 and 0, each panel fetched one and a half panels ahead (two
+    // register staging sets)
+    {12, 64, 64, 32, 32, 32},
+    {13, 128, 64, 32, 64, 32},
+    {14, 128, 128, 32, 64, 64},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -70,6 +75,9 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 9: return launch_sgemm_direct(cfg, ta, tb, g, stream);
     case 10:
     case 11: return launch_sgemm_valu(cfg, ta, tb, g, stream);
+    case 12: return launch_sgemm_cfg<64, 64, 32, 32, 32, true>(ta, tb, g, stream);
+    case 13: return launch_sgemm_cfg<128, 64, 32, 64, 32, true>(ta, tb, g, stream);
+    case 14: return launch_sgemm_cfg<128, 128, 32, 64, 64, true>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

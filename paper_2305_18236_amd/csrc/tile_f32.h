@@ -45,6 +45,8 @@
 // MFMA 32x32x2 f32 operand layout (per lane l of 64): A supplies
 // op(A)[row l%32][k l/32], B supplies op(B)[k l/32][col l%32]; result register
 // r of lane l is C[row 8*(r/4) + 4*(l/32) + r%4][col l%32].
+#include <type_traits>
+
 #include "common.h"
 
 namespace mg {
@@ -154,7 +156,13 @@ constexpr int sgemm_lds_floats() { return 2 * BK * (BM + BN); }
 // the same registers: alpha*(X Y^T + Y X^T) for the symmetric rank-2k update
 // of Section 5.1 (M == N, both operands of one shape).  UPLO 1 (2) stores
 // only the entries with m >= n (m <= n) of the tile.
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SYR2K = false, int UPLO = 0>
+//
+// DEEP: two register staging sets, so each panel is fetched one and a half
+// panels before it is packed (instead of half a panel).  The small tiles
+// (one wave per SIMD, a short K loop per panel) otherwise wait out most of a
+// global load's latency on every panel; their staging sets are small.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SYR2K = false, int UPLO = 0,
+          bool DEEP = false>
 MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
 {
     constexpr int WAVES_N = BN / WN;
@@ -182,30 +190,34 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
     // Stored panels: A is M x K ('N') or K x M ('T'); B is K x N ('N') or N x K ('T').
     using LA = PanelLoader<TA ? BK : BM, TA ? BM : BK, NT>;
     using LB = PanelLoader<TB ? BN : BK, TB ? BK : BN, NT>;
-    LA la;
-    LB lb;
+    LA la[DEEP ? 2 : 1];
+    LB lb[DEEP ? 2 : 1];
     const int64_t Ra = TA ? g.K : g.M, Ca = TA ? g.M : g.K;
     const int64_t Rb = TB ? g.N : g.K, Cb = TB ? g.K : g.N;
 
     // Panel p of the K loop: segment p / nk (SYR2K's second product swaps
     // the operands), k0 = (p % nk) * BK.
     const int nk = int((g.K + BK - 1) / BK);
-    auto fetch = [&](int p) {
+    // set: the staging set (a compile-time constant, so the sets stay in
+    // registers)
+    auto fetch = [&](int p, auto set) {
         const bool swap = SYR2K && p >= nk;
         const int64_t k0 = int64_t(swap ? p - nk : p) * BK;
         const float* __restrict__ xa = swap ? g.B : g.A;
         const float* __restrict__ xb = swap ? g.A : g.B;
         const int64_t lxa = swap ? g.ldb : g.lda, lxb = swap ? g.lda : g.ldb;
         const bool va = swap ? g.vec_b : g.vec_a, vb = swap ? g.vec_a : g.vec_b;
-        if (TA) la.load(xa, lxa, k0, m0, Ra, Ca, va, tid);
-        else    la.load(xa, lxa, m0, k0, Ra, Ca, va, tid);
-        if (TB) lb.load(xb, lxb, n0, k0, Rb, Cb, vb, tid);
-        else    lb.load(xb, lxb, k0, n0, Rb, Cb, vb, tid);
+        if (TA) la[set].load(xa, lxa, k0, m0, Ra, Ca, va, tid);
+        else    la[set].load(xa, lxa, m0, k0, Ra, Ca, va, tid);
+        if (TB) lb[set].load(xb, lxb, n0, k0, Rb, Cb, vb, tid);
+        else    lb[set].load(xb, lxb, k0, n0, Rb, Cb, vb, tid);
     };
-    auto pack = [&](int buf) {
-        la.template store<TA, BM>(As[buf], tid);
-        lb.template store<!TB, BN>(Bs[buf], tid);
+    auto pack = [&](int buf, auto set) {
+        la[set].template store<TA, BM>(As[buf], tid);
+        lb[set].template store<!TB, BN>(Bs[buf], tid);
     };
+    using Set0 = std::integral_constant<int, 0>;
+    using Set1 = std::integral_constant<int, DEEP ? 1 : 0>;
 
     floatx16 acc[V][H];
 #pragma unroll
@@ -223,17 +235,29 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
         p0 = int(blockIdx.y * g.k_chunk);
         p1 = min(p1, int(p0 + g.k_chunk));
     }
+    // Panel p is staged in set (p - p0) & 1 (DEEP) or set 0, and multiplied
+    // from LDS buffer (p - p0) & 1.
     if (p0 < p1) {
-        fetch(p0);
-        pack(0);
+        fetch(p0, Set0{});
+        pack(0, Set0{});
+        if (DEEP && p0 + 1 < p1) fetch(p0 + 1, Set1{});
     }
     __syncthreads();
 
     constexpr int STEPS = BK / 2;          // MFMA k-steps per panel
     constexpr int PACK_AT = STEPS / 2;     // the next panel is packed half-way
-    for (int kt = p0; kt < p1; ++kt) {
-        const int cur = (kt - p0) & 1;
-        if (kt + 1 < p1) fetch(kt + 1);
+    // One panel: LDS buffer cur holds panel kt.  DEEP: fetch panel kt + 2
+    // into set_cur (its panel kt went to LDS one iteration ago) and pack
+    // panel kt + 1 from set_next; otherwise fetch panel kt + 1 into the one
+    // set and pack it half-way.
+    auto panel = [&](int kt, int cur, auto set_cur, auto set_next) {
+        using SetNext = decltype(set_next);
+        using SetCur = decltype(set_cur);
+        if (DEEP) {
+            if (kt + 2 < p1) fetch(kt + 2, SetCur{});
+        } else {
+            if (kt + 1 < p1) fetch(kt + 1, SetCur{});
+        }
 
         const float* a_rows = As[cur] + h * BM;
         const float* b_rows = Bs[cur] + h * BN;
@@ -256,10 +280,10 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
                 lds_read<H>(b_at(s + 1), bn);
             }
             if (s == PACK_AT) {
-                // Pack the panel fetched at the top of this iteration into the
-                // other LDS buffer (last read before the previous barrier).
-                // On the last panel this rewrites stale data nobody reads.
-                pack(cur ^ 1);
+                // Pack panel kt + 1 into the other LDS buffer (last read
+                // before the previous barrier).  On the last panel this
+                // rewrites stale data nobody reads.
+                pack(cur ^ 1, SetNext{});
             }
 #pragma unroll
             for (int i = 0; i < V; ++i)
@@ -274,6 +298,16 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
             }
         }
         __syncthreads();
+    };
+    if constexpr (DEEP) {
+        // unrolled by two so that the staging set of each panel is a
+        // compile-time choice
+        for (int kt = p0; kt < p1; kt += 2) {
+            panel(kt, 0, Set0{}, Set1{});
+            if (kt + 1 < p1) panel(kt + 1, 1, Set1{}, Set0{});
+        }
+    } else {
+        for (int kt = p0; kt < p1; ++kt) panel(kt, (kt - p0) & 1, Set0{}, Set0{});
     }
 
     // Epilogue: C = alpha*acc + beta*C0, once per element.  C0 is read

@@ -89,7 +89,9 @@ def test_config_registry(native):
     packs = [native.mg_config_packs(0, i) for i in range(n)]
     assert set(packs) == {0, 1} and packs[:8] == [1] * 8
     mfma = [native.mg_config_uses_mfma(0, i) for i in range(n)]
-    assert mfma[:10] == [1] * 10 and set(mfma[10:]) == {0}
+    # 10 and 11 run the vector-ALU micro-kernel, every other one the matrix cores
+    assert mfma[:10] == [1] * 10 and mfma[10:12] == [0, 0] and set(mfma[12:]) <= {1}
+    assert packs[12:] == [1] * (n - 12)
     assert native.mg_config_uses_mfma(0, n) == -101
     assert native.mg_config_packs(0, n) == -101 and native.mg_config_packs(1, 0) == 1
     assert native.mg_force_config(0, n) == -101

@@ -55,7 +55,7 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     """Each tile configuration over several tiles and a ragged tail (8 and 9

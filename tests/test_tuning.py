@@ -220,11 +220,12 @@ def test_fp32_round_plan(rule):
     assert plan(4096, 4096, 1024) == (5, 1)
     assert plan(256, 8192, 8192) == (5, 8)
     assert plan(8192, 8192, 256) == (4, 1)
-    assert plan(1024, 1024, 1024) == (3, 1)
-    assert plan(3072, 3072, 3072) == (3, 1)
+    # the 64 x 64 tile runs as its two-staging-set form (12)
+    assert plan(1024, 1024, 1024) == (12, 1)
+    assert plan(3072, 3072, 3072) == (12, 1)
     assert plan(6144, 6144, 6144) == (5, 4)
-    assert plan(1536, 1536, 1536) == (3, 4)
-    assert plan(1536, 1536, 4096) == (3, 4)
+    assert plan(1536, 1536, 1536) == (12, 4)
+    assert plan(1536, 1536, 4096) == (12, 4)
     # the workspace query follows the plan's K ranges
     assert native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 4096) == 4 * 1536 * 1536 * 4
 
