@@ -5,32 +5,32 @@
 
 namespace mg {
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool DEEP>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool DEEP, int KG>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64 * KG)
 void sgemm_mfma_kernel(GemmArgs args)
 {
-    __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<BM, BN, BK>()];
+    __shared__ __attribute__((aligned(16))) float smem[sgemm_lds_floats<BM, BN, BK, KG>()];
     GemmArgs g = args;
     split_k_view<TA, TB, false>(g);
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, g.group_m, g.remap, tm, tn);
-    sgemm_tile<BM, BN, BK, WM, WN, TA, TB, false, 0, DEEP>(g, tm, tn, smem);
+    sgemm_tile<BM, BN, BK, WM, WN, TA, TB, false, 0, DEEP, KG>(g, tm, tn, smem);
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers, one per tile configuration.
 
-template <int BM, int BN, int BK, int WM, int WN, bool DEEP = false>
+template <int BM, int BN, int BK, int WM, int WN, bool DEEP = false, int KG = 1>
 static hipError_t launch_sgemm_cfg(bool ta, bool tb, GemmArgs g, hipStream_t stream)
 {
-    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    constexpr int NT = (BM / WM) * (BN / WN) * 64 * KG;
     g.tiles_m = int((g.M + BM - 1) / BM);
     g.tiles_n = int((g.N + BN - 1) / BN);
     const dim3 grid(g.tiles_m * g.tiles_n, split_count(g)), block(NT);
-    if (!ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, false, DEEP>), grid, block, 0, stream, g);
-    else if (!ta && tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, true, DEEP>), grid, block, 0, stream, g);
-    else if (ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, false, DEEP>), grid, block, 0, stream, g);
-    else hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, true, DEEP>), grid, block, 0, stream, g);
+    if (!ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, false, DEEP, KG>), grid, block, 0, stream, g);
+    else if (!ta && tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, false, true, DEEP, KG>), grid, block, 0, stream, g);
+    else if (ta && !tb) hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, false, DEEP, KG>), grid, block, 0, stream, g);
+    else hipLaunchKernelGGL((sgemm_mfma_kernel<BM, BN, BK, WM, WN, true, true, DEEP, KG>), grid, block, 0, stream, g);
     return hipGetLastError();
 }
 
@@ -57,6 +57,10 @@ const SgemmConfig kSgemmConfigs[] = {
     {12, 64, 64, 32, 32, 32},
     {13, 128, 64, 32, 64, 32},
     {14, 128, 128, 32, 64, 64},
+    // as 12 and 13 with two K groups of waves in the workgroup (each group
+    // every other panel, sums added through LDS): two waves per SIMD
+    {15, 64, 64, 32, 32, 32},
+    {16, 128, 64, 32, 64, 32},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -78,6 +82,8 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 12: return launch_sgemm_cfg<64, 64, 32, 32, 32, true>(ta, tb, g, stream);
     case 13: return launch_sgemm_cfg<128, 64, 32, 64, 32, true>(ta, tb, g, stream);
     case 14: return launch_sgemm_cfg<128, 128, 32, 64, 64, true>(ta, tb, g, stream);
+    case 15: return launch_sgemm_cfg<64, 64, 32, 32, 32, true, 2>(ta, tb, g, stream);
+    case 16: return launch_sgemm_cfg<128, 64, 32, 64, 32, true, 2>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

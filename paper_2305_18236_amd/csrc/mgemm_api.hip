@@ -341,8 +341,19 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 // The 64 x 64 FP32 tile with two register staging sets (12) replaces the
 // one-set form (3) wherever the rule picks that tile: measured (NN, beta
 // 0.5, % of the FP32 peak) 1024^3 46.2 -> 50.9, 1536^3 in four K ranges
-// 55.7 -> 56.4, 3072^3 71.2 -> 74.3.
-int fp32_deep(int cfg) { return cfg == 3 ? 12 : cfg; }
+// 55.7 -> 56.4, 3072^3 71.2 -> 74.3.  When its workgroups (tiles times K
+// ranges) give each compute unit at most one, the form with two K groups of
+// waves (15) takes it instead, two waves per SIMD where the others have
+// one: 1024^3 50.9 -> 54.3 (at 2048^3 and 3072^3, several workgroups per
+// compute unit, the two tie).
+int fp32_small_tile(int cfg, int64_t M, int64_t N, int64_t K, int splits, bool split_ok)
+{
+    if (cfg != 3) return cfg;
+    const int64_t cus = device_cus();
+    const int64_t t = tiles(M, N, 64, 64);
+    const int64_t s = splits > 0 ? effective_splits(K, splits) : (split_ok ? effective_splits(K, auto_splits(t, K)) : 1);
+    return t * s <= cus ? 15 : 12;
+}
 
 int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
 {
@@ -375,7 +386,9 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
     // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
     if (path == MG_PATH_FP32 && std::max({M, N, K}) <= 32) return 8;
     const int pick = ladder_choice(path, M, N, K, cus, split_ok);
-    return path == MG_PATH_FP32 ? fp32_deep(fp32_plan(M, N, K, pick, split_ok).cfg) : pick;
+    if (path != MG_PATH_FP32) return pick;
+    const Fp32Plan fp = fp32_plan(M, N, K, pick, split_ok);
+    return fp32_small_tile(fp.cfg, M, N, K, fp.splits, split_ok);
 }
 
 int pick_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok = true);
@@ -478,7 +491,7 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool sp
     if (s < 0 && path == MG_PATH_FP32) {
         // the K ranges the round plan chose with this configuration
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
-        if (fp.cfg == cfg || fp32_deep(fp.cfg) == cfg) s = fp.splits;
+        if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15))) s = fp.splits;
     }
     if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)
                                         : splits_16bit(tiles(M, N, c.bm, c.bn), K, device_cus());

@@ -141,9 +141,10 @@ MG_DEVICE void lds_read(const float* p, float (&out)[V])
 }
 
 // ---------------------------------------------------------------------------
-// LDS floats one tile configuration needs (two stages of both panels).
-template <int BM, int BN, int BK>
-constexpr int sgemm_lds_floats() { return 2 * BK * (BM + BN); }
+// LDS floats one tile configuration needs (two stages of both panels, per
+// K group).
+template <int BM, int BN, int BK, int KG = 1>
+constexpr int sgemm_lds_floats() { return KG * 2 * BK * (BM + BN); }
 
 // One BM x BN output tile (tm, tn) of the GEMM in g, computed by the whole
 // workgroup ((BM/WM) * (BN/WN) waves).  smem: sgemm_lds_floats() floats of LDS,
@@ -161,22 +162,33 @@ constexpr int sgemm_lds_floats() { return 2 * BK * (BM + BN); }
 // panels before it is packed (instead of half a panel).  The small tiles
 // (one wave per SIMD, a short K loop per panel) otherwise wait out most of a
 // global load's latency on every panel; their staging sets are small.
+//
+// KG > 1: the workgroup is KG groups of (BM/WM) * (BN/WN) waves; group q
+// multiplies the panels p0 + q, p0 + q + KG, ... out of its own LDS buffers
+// into its own accumulators, and at the end the groups' sums are added
+// through LDS (group 0 first, then 1, ...) before group 0's epilogue.  A
+// small tile then has KG waves per SIMD to hide latency with, without a
+// second launch for a split K.  (GEMM only: SYR2K keeps KG = 1.)
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SYR2K = false, int UPLO = 0,
-          bool DEEP = false>
+          bool DEEP = false, int KG = 1>
 MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
 {
+    static_assert(KG == 1 || !SYR2K, "SYR2K runs one K group");
     constexpr int WAVES_N = BN / WN;
-    constexpr int NT = (BM / WM) * WAVES_N * 64;
+    constexpr int NT = (BM / WM) * WAVES_N * 64;   // threads of one K group
     constexpr int V = WM / 32;   // accumulator row blocks per wave
     constexpr int H = WN / 32;   // accumulator column blocks per wave
     static_assert(V == 1 || V == 2 || V == 4, "WM must be 32, 64 or 128");
     static_assert(H == 1 || H == 2 || H == 4, "WN must be 32, 64 or 128");
     static_assert(BK % 2 == 0, "BK must be a multiple of the MFMA depth");
 
-    float (*As)[BK * BM] = reinterpret_cast<float (*)[BK * BM]>(smem);
-    float (*Bs)[BK * BN] = reinterpret_cast<float (*)[BK * BN]>(smem + 2 * BK * BM);
+    // K group of this wave (uniform across the wave) and its LDS buffers
+    const int grp = KG > 1 ? int(threadIdx.x) / NT : 0;
+    float* gsmem = smem + grp * (2 * BK * (BM + BN));
+    float (*As)[BK * BM] = reinterpret_cast<float (*)[BK * BM]>(gsmem);
+    float (*Bs)[BK * BN] = reinterpret_cast<float (*)[BK * BN]>(gsmem + 2 * BK * BM);
 
-    const int tid = threadIdx.x;
+    const int tid = KG > 1 ? int(threadIdx.x) % NT : int(threadIdx.x);   // thread within the group
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm0 = (wave / WAVES_N) * WM;
@@ -235,12 +247,18 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
         p0 = int(blockIdx.y * g.k_chunk);
         p1 = min(p1, int(p0 + g.k_chunk));
     }
-    // Panel p is staged in set (p - p0) & 1 (DEEP) or set 0, and multiplied
-    // from LDS buffer (p - p0) & 1.
+    // This group's panels: p0 + grp, then every KG-th.  With KG > 1 the
+    // loop below indexes them by their position i = 0, 1, ... in the
+    // group's sequence and the groups run the same number of iterations
+    // (a group past its last panel only joins the barriers).
+    p0 += grp;
+    const int step = KG;
+    // Panel p is staged in set ((p - p0) / KG) & 1 (DEEP) or set 0, and
+    // multiplied from LDS buffer ((p - p0) / KG) & 1 of the group.
     if (p0 < p1) {
         fetch(p0, Set0{});
         pack(0, Set0{});
-        if (DEEP && p0 + 1 < p1) fetch(p0 + 1, Set1{});
+        if (DEEP && p0 + step < p1) fetch(p0 + step, Set1{});
     }
     __syncthreads();
 
@@ -253,10 +271,15 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
     auto panel = [&](int kt, int cur, auto set_cur, auto set_next) {
         using SetNext = decltype(set_next);
         using SetCur = decltype(set_cur);
+        if (KG > 1 && kt >= p1) {
+            // this group has no panel left: only the barrier
+            __syncthreads();
+            return;
+        }
         if (DEEP) {
-            if (kt + 2 < p1) fetch(kt + 2, SetCur{});
+            if (kt + 2 * step < p1) fetch(kt + 2 * step, SetCur{});
         } else {
-            if (kt + 1 < p1) fetch(kt + 1, SetCur{});
+            if (kt + step < p1) fetch(kt + step, SetCur{});
         }
 
         const float* a_rows = As[cur] + h * BM;
@@ -299,7 +322,47 @@ MG_DEVICE void sgemm_tile(const GemmArgs& g, int tm, int tn, float* smem)
         }
         __syncthreads();
     };
-    if constexpr (DEEP) {
+    if constexpr (KG > 1) {
+        // every group runs the iterations of group 0, which has the most panels
+        const int base = p0 - grp;
+        const int iters = base < p1 ? (p1 - base + KG - 1) / KG : 0;
+        if constexpr (DEEP) {
+            for (int i = 0; i < iters; i += 2) {
+                panel(p0 + i * step, 0, Set0{}, Set1{});
+                if (i + 1 < iters) panel(p0 + (i + 1) * step, 1, Set1{}, Set0{});
+            }
+        } else {
+            for (int i = 0; i < iters; ++i) panel(p0 + i * step, i & 1, Set0{}, Set0{});
+        }
+        // Add the groups' sums through LDS (free after the loop's last
+        // barrier): group q > 0 stores its accumulators in turn, group 0
+        // adds them, in the order q = 1, 2, ...
+        float* red = smem;
+        static_assert(BM * BN <= KG * 2 * BK * (BM + BN), "reduction fits the panel buffers");
+        const int slot0 = ((wave * V * H) * 16) * 64 + lane;
+#pragma unroll 1
+        for (int q = 1; q < KG; ++q) {
+            if (grp == q) {
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) red[slot0 + ((i * H + j) * 16 + r) * 64] = acc[i][j][r];
+            }
+            __syncthreads();
+            if (grp == 0) {
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+#pragma unroll
+                    for (int j = 0; j < H; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[i][j][r] += red[slot0 + ((i * H + j) * 16 + r) * 64];
+            }
+            __syncthreads();
+        }
+        if (grp != 0) return;
+    } else if constexpr (DEEP) {
         // unrolled by two so that the staging set of each panel is a
         // compile-time choice
         for (int kt = p0; kt < p1; kt += 2) {

@@ -105,7 +105,7 @@ def test_ragged_shapes_all_layouts(gpu, path, tA, tB, M, N, K):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, path, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, path, cfg=cfg)
@@ -123,7 +123,7 @@ def test_prepacked_and_in_kernel_conversion(gpu, path, tA, tB, use_workspace):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_prepacked_every_config(gpu, path, cfg):
     _check(Problem(777, 531, 203, "T", "N", -1.0, 0.25, seed=100 + cfg), gpu, path, cfg=cfg)
 

@@ -55,13 +55,42 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     """Each tile configuration over several tiles and a ragged tail (8 and 9
     without packing, 10 and 11 with the vector-ALU micro-kernel)."""
     p = Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg * 4 + ord(tA) + ord(tB))
     _check(p, gpu, cfg=cfg)
+
+
+@pytest.mark.parametrize("deep,single", [(12, 3), (13, 4), (14, 0)])
+@pytest.mark.parametrize("tA,tB", LAYOUTS)
+def test_two_staging_sets_bit_identical(gpu, deep, single, tA, tB):
+    """Configurations 12-14 are 3, 4 and 0 with each panel fetched a panel
+    earlier into a second register staging set: the same products in the
+    same order, so the same bits (odd and even panel counts, ragged edges)."""
+    for K in (77, 160, 1000):
+        C1, _, _ = _check(Problem(300, 260, K, tA, tB, 1.5, 0.5, seed=K + deep), gpu, cfg=single)
+        C2, _, _ = _check(Problem(300, 260, K, tA, tB, 1.5, 0.5, seed=K + deep), gpu, cfg=deep)
+        assert np.array_equal(C1, C2), (deep, K, tA, tB)
+
+
+@pytest.mark.parametrize("cfg", [15, 16])
+@pytest.mark.parametrize("K", [1, 32, 33, 64, 96, 1000])
+def test_k_groups_every_panel_count(gpu, cfg, K):
+    """Two K groups of waves per workgroup (each every other 32-deep panel,
+    sums added through LDS): one panel (the second group idles), two, three
+    and many, ragged K."""
+    _check(Problem(300, 260, K, "N", "T", 1.5, 0.5, seed=K + 7 * cfg), gpu, cfg=cfg)
+
+
+@pytest.mark.parametrize("cfg", [15, 16])
+def test_k_groups_integer_bit_exact(gpu, cfg):
+    """Integer inputs: every partial sum is exact, so the two groups' sums
+    and their addition give the exact result."""
+    C, Cref, _ = _check(Problem(330, 270, 250, "T", "N", 1.5, 0.5, seed=3 + cfg, dist="integers"), gpu, cfg=cfg)
+    assert np.array_equal(C, Cref)
 
 
 @pytest.mark.parametrize("tA,tB", LAYOUTS)

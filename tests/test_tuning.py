@@ -220,8 +220,9 @@ def test_fp32_round_plan(rule):
     assert plan(4096, 4096, 1024) == (5, 1)
     assert plan(256, 8192, 8192) == (5, 8)
     assert plan(8192, 8192, 256) == (4, 1)
-    # the 64 x 64 tile runs as its two-staging-set form (12)
-    assert plan(1024, 1024, 1024) == (12, 1)
+    # the 64 x 64 tile runs as its two-staging-set form (12), or with two K
+    # groups (15) where its workgroups give each compute unit at most one
+    assert plan(1024, 1024, 1024) == (15, 1)   # one workgroup per compute unit: two K groups
     assert plan(3072, 3072, 3072) == (12, 1)
     assert plan(6144, 6144, 6144) == (5, 4)
     assert plan(1536, 1536, 1536) == (12, 4)
