@@ -162,18 +162,20 @@ class Bench:
                 self.torch.cuda.synchronize()
         self.torch.cuda.synchronize()
 
-    def steps(self, fn, steps, probe=False):
-        """`steps` back-to-back calls with a HIP event between consecutive
-        calls on the launch stream; returns (per-step ms list, total ms,
-        clock during the steps).  probe: once the steps are queued, the clock
-        probe runs on the side stream, beside them when the GPU has room for
-        its 16 one-wave workgroups; its reading counts as taken during the
-        steps only if the launch stream is still busy when it returns."""
+    def steps(self, fn, steps, probe=False, calls=1):
+        """`steps` samples of `calls` back-to-back calls each, with a HIP
+        event between consecutive samples on the launch stream; returns
+        (per-call ms of each sample, total ms, clock during the samples).
+        probe: once the samples are queued, the clock probe runs on the side
+        stream, beside them when the GPU has room for its 16 one-wave
+        workgroups; its reading counts as taken during the samples only if
+        the launch stream is still busy when it returns."""
         torch = self.torch
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         ev[0].record(self.stream)
         for i in range(steps):
-            fn()
+            for _ in range(calls):
+                fn()
             ev[i + 1].record(self.stream)
         during = None
         if probe:
@@ -181,7 +183,7 @@ class Bench:
             if st == 0 and not self.stream.query():
                 during = round(mhz, 1)
         torch.cuda.synchronize()
-        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        per = [ev[i].elapsed_time(ev[i + 1]) / calls for i in range(steps)]
         return per, ev[0].elapsed_time(ev[steps]), during
 
     def per_launch(self, fn, steps, between=None):
@@ -211,16 +213,34 @@ class Bench:
         _, _, during = self.steps(fn, n, probe=True)
         return during
 
+    def calls_per_sample(self, fn):
+        """Calls per timed sample: 1 for calls of 0.1 ms and more; shorter
+        calls are timed in back-to-back blocks of about 0.5 ms, since an
+        event between every two calls adds its own gap (a 25 us GEMM: about
+        2.5 us) to each."""
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(4):
+            fn()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 4
+        return 1 if t >= 0.1 else max(1, min(200, int(0.5 / max(t, 1e-4))))
+
     def case(self, fn, steps=None, warmup=None):
-        """Warm up, time `steps` calls, read the clock right after them, then
-        the clock under the same load (outside the timed steps, so that the
-        probe's workgroups never share the GPU with a timed step)."""
+        """Warm up, time `steps` samples (single calls, or blocks of calls
+        for short ones), read the clock right after them, then the clock
+        under the same load (outside the timed samples, so that the probe's
+        workgroups never share the GPU with a timed one)."""
         steps = self.args.steps if steps is None else steps
         warmup = self.args.warmup if warmup is None else warmup
         self.warm(fn, warmup)
-        per, total, _ = self.steps(fn, steps)
+        calls = self.calls_per_sample(fn)
+        per, total, _ = self.steps(fn, steps, calls=calls)
         after = self.sclk()
-        return {"per_ms": per, "total_ms": total, "sclk_mhz": after, "sclk_mhz_during": self.load_clock(fn, per)}
+        return {"per_ms": per, "total_ms": total, "sclk_mhz": after, "calls_per_sample": calls,
+                "sclk_mhz_during": self.load_clock(fn, per)}
 
     def gemm_call(self, path, tA, tB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws=None):
         """A closure launching mg_gemm with its full workspace (allocated here once)."""
@@ -487,7 +507,7 @@ def bench_sweep(bench, si):
                            torch.from_numpy(C0_h).to(dev), torch.from_numpy(C0_h).to(dev))
     cases = [("fp32", s, tA + tB) for s in SWEEP_SHAPES for tA in "NT" for tB in "NT"]
     cases += [("bf16x3", s, "NN") for s in SWEEP_SHAPES]
-    runs, samples, clocks = {}, {c: [] for c in cases}, {c: [] for c in cases}
+    runs, samples, clocks, calls = {}, {c: [] for c in cases}, {c: [] for c in cases}, {}
     for rnd in range(args.rounds):
         progress(f"round {rnd + 1}/{args.rounds}")
         for case in bench.shuffled(cases):
@@ -500,6 +520,7 @@ def bench_sweep(bench, si):
             r = bench.case(runs[case])
             samples[case] += r["per_ms"]
             clocks[case].append([r["sclk_mhz_during"], r["sclk_mhz"]])
+            calls[case] = r["calls_per_sample"]
     rows = []
     for case in cases:
         path, (m, n, k), lay = case
@@ -519,7 +540,7 @@ def bench_sweep(bench, si):
         rows.append({"M": m, "N": n, "K": k, "path": path, "layout": lay, "ms": round(ms, 5),
                      "tflops": round(tflops(flops, ms), 2),
                      "pct_fp32_peak": round(100 * tflops(flops, ms) / PEAK_TFLOPS["fp32"], 1),
-                     "step_ms": stats(samples[case]), "sclk_mhz": clocks[case],
+                     "step_ms": stats(samples[case]), "calls_per_sample": calls[case], "sclk_mhz": clocks[case],
                      "config": cfg, "splits": splits, "prepacked": packed,
                      "sampled_error_vs_fp64_oracle": oracle_error(lay[0], lay[1], m, n, k, ALPHA, A_h, lda, B_h, ldb,
                                                                   BETA, C0_h, got, I, J)})
