@@ -89,6 +89,12 @@ def measured_traffic(profile=PROFILE_TRAFFIC):
         return None
 
 
+def native_plan_config(bench, M, N, K):
+    """The FP32 configuration mg_gemm runs for an M x N x K problem (no workspace)."""
+    st, cfg, _, _ = bench.native.mg_gemm_plan(PATH_ID["fp32"], M, N, K, 0)
+    return cfg if st == 0 else -1
+
+
 # ------------------------------------------------------------ statistics ---
 
 def ci95(samples):
@@ -419,6 +425,7 @@ def bench_sgemm(bench, si):
         res[path] = bench.case(run)
         del C, run
     f32 = res["fp32"]
+    f32_cfg = native_plan_config(bench, M, N, K)
     ms = f32["total_ms"] / args.steps
     achieved = tflops(flops, float(np.mean(f32["per_ms"])))
     peak = PEAK_TFLOPS["fp32"]
@@ -428,7 +435,8 @@ def bench_sgemm(bench, si):
     out["pct_fp32_mfma_peak"] = round(100.0 * tflops(flops, ms) / peak, 2)
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                        "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
-                       "kernel": "sgemm_mfma_kernel<256,256,16,128,64,NN>",
+                       "kernel": "sgemm_mfma_kernel<256,256,16,128,64,NN> (configuration %d%s)" % (
+                           f32_cfg, ", two register staging sets" if f32_cfg == 17 else ""),
                        "kernel_ms_mean": round(float(np.mean(f32["per_ms"])), 4),
                        "algorithmic_flops_per_launch": flops}
     out["step_time_ms"] = {p: stats(r["per_ms"]) for p, r in res.items()}

@@ -61,6 +61,8 @@ const SgemmConfig kSgemmConfigs[] = {
     // every other panel, sums added through LDS): two waves per SIMD
     {15, 64, 64, 32, 32, 32},
     {16, 128, 64, 32, 64, 32},
+    // as 5 with two register staging sets
+    {17, 256, 256, 16, 128, 64},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -84,6 +86,7 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 14: return launch_sgemm_cfg<128, 128, 32, 64, 64, true>(ta, tb, g, stream);
     case 15: return launch_sgemm_cfg<64, 64, 32, 32, 32, true, 2>(ta, tb, g, stream);
     case 16: return launch_sgemm_cfg<128, 64, 32, 64, 32, true, 2>(ta, tb, g, stream);
+    case 17: return launch_sgemm_cfg<256, 256, 16, 128, 64, true>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -65,7 +65,9 @@ void syr2k_kernel(GemmArgs args)
     }
     // trans 'N': op(A) = X (stored N x K), op(B) = Y^T (Y stored N x K);
     // trans 'T': op(A) = X^T (stored K x N), op(B) = Y (stored K x N).
-    sgemm_tile<BT, BT, BK, WM, WN, TR, !TR, true, UPLO>(g, tm, tn, smem);
+    // Two register staging sets (each panel fetched one and a half panels
+    // before it is packed), as the GEMM's 256 x 256 tile.
+    sgemm_tile<BT, BT, BK, WM, WN, TR, !TR, true, UPLO, true>(g, tm, tn, smem);
 }
 
 template <int BT, int BK, int WM, int WN>

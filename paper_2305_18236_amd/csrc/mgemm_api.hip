@@ -346,8 +346,13 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 // waves (15) takes it instead, two waves per SIMD where the others have
 // one: 1024^3 50.9 -> 54.3 (at 2048^3 and 3072^3, several workgroups per
 // compute unit, the two tie).
+// Likewise the 256 x 256 tile runs as its two-staging-set form (17):
+// measured against configuration 5 (% of the FP32 peak, same box, three
+// shuffled rounds): 8192^3 85.8 -> 88.2, 4096^3 84.5 -> 86.5,
+// 16384 x 1024 x 4096 84.2 -> 86.4, 6144^3 in four K ranges 79.8 -> 81.9.
 int fp32_small_tile(int cfg, int64_t M, int64_t N, int64_t K, int splits, bool split_ok)
 {
+    if (cfg == 5) return 17;
     if (cfg != 3) return cfg;
     const int64_t cus = device_cus();
     const int64_t t = tiles(M, N, 64, 64);
@@ -491,7 +496,7 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool sp
     if (s < 0 && path == MG_PATH_FP32) {
         // the K ranges the round plan chose with this configuration
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
-        if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15))) s = fp.splits;
+        if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15)) || (fp.cfg == 5 && cfg == 17)) s = fp.splits;
     }
     if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)
                                         : splits_16bit(tiles(M, N, c.bm, c.bn), K, device_cus());

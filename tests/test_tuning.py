@@ -214,17 +214,18 @@ def test_fp32_round_plan(rule):
     288 workgroups of 256 x 256 on 256 compute units before); shapes whose
     rounds come out whole keep the ladder's choice."""
     plan = lambda *s: (native.mg_tuned_config(0, *s), native.mg_split_count(0, *s))
-    assert plan(8192, 8192, 8192) == (5, 1)
-    assert plan(4096, 4096, 4096) == (5, 1)
-    assert plan(2048, 2048, 2048) == (5, 4)
-    assert plan(4096, 4096, 1024) == (5, 1)
-    assert plan(256, 8192, 8192) == (5, 8)
+    # the 256 x 256 tile runs as its two-staging-set form (17)
+    assert plan(8192, 8192, 8192) == (17, 1)
+    assert plan(4096, 4096, 4096) == (17, 1)
+    assert plan(2048, 2048, 2048) == (17, 4)
+    assert plan(4096, 4096, 1024) == (17, 1)
+    assert plan(256, 8192, 8192) == (17, 8)
     assert plan(8192, 8192, 256) == (4, 1)
     # the 64 x 64 tile runs as its two-staging-set form (12), or with two K
     # groups (15) where its workgroups give each compute unit at most one
     assert plan(1024, 1024, 1024) == (15, 1)   # one workgroup per compute unit: two K groups
     assert plan(3072, 3072, 3072) == (12, 1)
-    assert plan(6144, 6144, 6144) == (5, 4)
+    assert plan(6144, 6144, 6144) == (17, 4)
     assert plan(1536, 1536, 1536) == (12, 4)
     assert plan(1536, 1536, 4096) == (12, 4)
     # the workspace query follows the plan's K ranges
@@ -266,7 +267,7 @@ def test_plan_without_workspace_is_chosen_for_an_unsplit_k_loop(rule):
     n = 6144
     full = native.mg_gemm_workspace_size(0, "N", "N", n, n, n)
     assert full > 0
-    assert native.mg_gemm_plan(0, n, n, n, full) == (0, 5, 4, 0)
+    assert native.mg_gemm_plan(0, n, n, n, full) == (0, 17, 4, 0)
     st, cfg, splits, packed = native.mg_gemm_plan(0, n, n, n, 0)
     assert (st, splits, packed) == (0, 1, 0)
     assert cfg == 0
