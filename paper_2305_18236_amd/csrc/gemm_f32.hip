@@ -63,6 +63,11 @@ const SgemmConfig kSgemmConfigs[] = {
     {16, 128, 64, 32, 64, 32},
     // as 5 with two register staging sets
     {17, 256, 256, 16, 128, 64},
+    // 128 x 128 tiles of eight waves (64 x 32 or 32 x 64 each) with two
+    // register staging sets: two waves per SIMD where configuration 0 and
+    // 14 (four 64 x 64 waves) have one
+    {18, 128, 128, 32, 64, 32},
+    {19, 128, 128, 32, 32, 64},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -87,6 +92,8 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 15: return launch_sgemm_cfg<64, 64, 32, 32, 32, true, 2>(ta, tb, g, stream);
     case 16: return launch_sgemm_cfg<128, 64, 32, 64, 32, true, 2>(ta, tb, g, stream);
     case 17: return launch_sgemm_cfg<256, 256, 16, 128, 64, true>(ta, tb, g, stream);
+    case 18: return launch_sgemm_cfg<128, 128, 32, 64, 32, true>(ta, tb, g, stream);
+    case 19: return launch_sgemm_cfg<128, 128, 32, 32, 64, true>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -274,7 +274,7 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
 // ladder's choice leaves its last round less than 80 % full, the plan below
 // compares the 256 x 256, 128 x 128 and 64 x 64 tiles with 1-8 K ranges by
 // a time model fitted to MI355X measurements (per compute unit: 0.55,
-// 0.494, 0.483 TFLOP/s and 32, 8, 2 us of fixed cost per round of 1, 2, 5
+// 0.509, 0.483 TFLOP/s and 32, 9.5, 2 us of fixed cost per round of 1, 2, 5
 // resident workgroups, half that for split workgroups, which do not read C;
 // the reduction streams the partials and C at 5 TB/s, plus 5 us), and takes
 // the best if it is 5 % faster.
@@ -296,8 +296,12 @@ double fp32_model_us(int cfg, int64_t M, int64_t N, int64_t K, int64_t s, int64_
 {
     const int bm = cfg == 5 ? 256 : cfg == 0 ? 128 : 64;
     const int64_t occ = cfg == 5 ? 1 : cfg == 0 ? 2 : 5;
-    const double rate = cfg == 5 ? 0.55 : cfg == 0 ? 0.494 : 0.483;   // TFLOP/s per compute unit
-    const double fixed = cfg == 5 ? 32.0 : cfg == 0 ? 8.0 : 2.0;      // us per round
+    // the 128 x 128 figures are configuration 18's (it runs wherever the
+    // plan picks that tile): 2048 x 2048 x 1024 75.3 us, 2048^3 141.3 us,
+    // 1024 x 2048 x 1024 in two K ranges 47.9 us; the model gives 75.4,
+    // 141.4 and 47.8
+    const double rate = cfg == 5 ? 0.55 : cfg == 0 ? 0.509 : 0.483;   // TFLOP/s per compute unit
+    const double fixed = cfg == 5 ? 32.0 : cfg == 0 ? 9.5 : 2.0;      // us per round
     const int64_t per_cu = (tiles(M, N, bm, bm) * s + cus - 1) / cus;
     const double wg_us = 2.0 * bm * bm * double((K + s - 1) / s) / (rate * 1e6);
     // a split's workgroups store partial products without reading C (half
@@ -350,9 +354,15 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 // measured against configuration 5 (% of the FP32 peak, same box, three
 // shuffled rounds): 8192^3 85.8 -> 88.2, 4096^3 84.5 -> 86.5,
 // 16384 x 1024 x 4096 84.2 -> 86.4, 6144^3 in four K ranges 79.8 -> 81.9.
+// And the 128 x 128 tile runs as eight 64 x 32 waves with two staging sets
+// (18), faster than the four-wave configuration 0 at every shape measured
+// with the same K ranges (NN, beta 0.5, us): 1024 x 4096 x 1024 94.7 ->
+// 75.4, 512 x 2048 x 2048 in four ranges 53.9 -> 46.3, 3072 x 4096 x 4096
+// 869 -> 821, 1792 x 1536 x 4096 in three ranges 211.5 -> 203.6.
 int fp32_small_tile(int cfg, int64_t M, int64_t N, int64_t K, int splits, bool split_ok)
 {
     if (cfg == 5) return 17;
+    if (cfg == 0) return 18;
     if (cfg != 3) return cfg;
     const int64_t cus = device_cus();
     const int64_t t = tiles(M, N, 64, 64);
@@ -496,7 +506,9 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool sp
     if (s < 0 && path == MG_PATH_FP32) {
         // the K ranges the round plan chose with this configuration
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
-        if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15)) || (fp.cfg == 5 && cfg == 17)) s = fp.splits;
+        if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15)) || (fp.cfg == 5 && cfg == 17) ||
+            (fp.cfg == 0 && cfg == 18))
+            s = fp.splits;
     }
     if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)
                                         : splits_16bit(tiles(M, N, c.bm, c.bn), K, device_cus());
