@@ -191,7 +191,7 @@ def tune_exact(paths, shapes=EXACT_SHAPES, reps=5, log=sys.stdout):
                 B = torch.rand(K * N, device=dev) * 2 - 1
                 C = torch.rand(M * N, device=dev) * 2 - 1
             default = _plan_now(pid, M, N, K)
-            cands = blocking.candidates(cfgs, M, N, K, keep=24)
+            cands = blocking.candidates(cfgs, M, N, K, keep=32)
             if default not in cands:
                 cands.append(default)
             results = []

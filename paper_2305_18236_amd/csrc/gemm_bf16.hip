@@ -213,6 +213,10 @@ const SgemmConfig kBf16Configs[] = {
     // one's epilogue overlaps the other's K loop when K is short); without
     // the planes it runs as configuration 2
     {7, 128, 128, 64, 64, 64},
+    // the 128 x 128 tile of configuration 2 over eight waves (64 x 32 or
+    // 32 x 64 each): two waves per SIMD
+    {8, 128, 128, 32, 64, 32},
+    {9, 128, 128, 32, 32, 64},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
@@ -232,6 +236,8 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 7:
         if (packed) return launch_bf16_direct<128, 128, 64, 64, TERMS>(g, stream);
         return launch_bf16_cfg<128, 128, 32, 64, 64, TERMS>(ta, tb, g, stream, packed);
+    case 8: return launch_bf16_cfg<128, 128, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
+    case 9: return launch_bf16_cfg<128, 128, 32, 32, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }

@@ -245,7 +245,18 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
             // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
             // M N >= 1250 (M + N) for bf16x3.
-            if (n * (split_ok ? splits_16bit(n, K, cus) : 1) * 2 < cus) continue;
+            const int s16 = split_ok ? splits_16bit(n, K, cus) : 1;
+            if (n * s16 * 2 < cus) continue;
+            // as for FP32 below: the 256 x 256 tile, when it needs K ranges
+            // as short as kMinRange, gives way to the 128 x 128 tile if that
+            // one fills the GPU unsplit (NN, beta 0.5, us: 2048 x 2048 x 1024
+            // bf16x3 51.4 -> 46.5, BF16 44.5 -> 26.9; 1024 x 4096 x 1024
+            // bf16x3 51.3 -> 47.0, BF16 46.1 -> 28.0).  The 128 x 128 tile
+            // keeps its split against the 64 x 64 one (bf16x3 1024^3: 25.0 us
+            // in four K ranges, 32.0 us unsplit on 64 x 64 tiles).
+            if (i == 0 && s16 > 1 && K / s16 <= kMinRange &&
+                tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn) >= cus)
+                return ladder[1];
             if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
                 (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
                 return 6;
@@ -401,6 +412,14 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
     // 0.95x at 32^3, even at 64^3, packing ahead from 128^3 on).
     if (path == MG_PATH_FP32 && std::max({M, N, K}) <= 32) return 8;
     const int pick = ladder_choice(path, M, N, K, cus, split_ok);
+    // BF16 and FP16 (one product per step) run the 128 x 128 tile as eight
+    // 32 x 64 waves (9): two waves per SIMD where configuration 2 has one,
+    // 4-10 % faster at every shape measured (us, configuration 2 -> 9, the
+    // same K ranges: 1024^3 26.3 -> 22.6, 2048^3 43.0 -> 39.9, 2048 x 2048 x
+    // 1024 30.1 -> 26.9, 2048 x 2048 x 8192 125.9 -> 113.1).  bf16x3's three
+    // products per step keep four waves busy (2048^3 in two K ranges: 70.1
+    // us against 77.2-78.4 with eight).
+    if (pick == 2 && (path == MG_PATH_BF16 || path == MG_PATH_FP16)) return 9;
     if (path != MG_PATH_FP32) return pick;
     const Fp32Plan fp = fp32_plan(M, N, K, pick, split_ok);
     return fp32_small_tile(fp.cfg, M, N, K, fp.splits, split_ok);
