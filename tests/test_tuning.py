@@ -230,6 +230,37 @@ def test_fp32_round_plan(rule):
     assert plan(1536, 1536, 4096) == (12, 4)
     # the workspace query follows the plan's K ranges
     assert native.mg_gemm_workspace_size(0, "N", "N", 1536, 1536, 4096) == 4 * 1536 * 1536 * 4
+    # the 128 x 128 tile runs as eight waves with two staging sets (18)
+    assert plan(1024, 4096, 1024) == (18, 1)
+    assert plan(2048, 2048, 1024) == (18, 1)
+    assert plan(512, 2048, 2048) == (18, 4)
+    assert plan(3072, 4096, 4096) == (18, 1)
+
+
+def test_fp32_model_of_the_eight_wave_tile(rule):
+    native = rule
+    """The round plan's model charges the 128 x 128 tile configuration 18's
+    measured rate: with the 2048^3 entry out of the way, 2048^3 still plans
+    the 256 x 256 tile in four K ranges (rounds already whole), while the
+    committed table takes configuration 18 unsplit there."""
+    assert (native.mg_tuned_config(0, 2048, 2048, 2048), native.mg_split_count(0, 2048, 2048, 2048)) == (17, 4)
+    native._load_default_tuning(native.lib())
+    assert native.mg_tuned_config(0, 2048, 2048, 2048) == 18
+
+
+def test_sixteen_bit_ladder_steps_down_from_short_k_ranges(rule):
+    native = rule
+    """Where 256 x 256 tiles would need 256-deep K ranges and unsplit 128 x 128
+    tiles fill the compute units, the 16-bit rule takes the 128 x 128 tile
+    unsplit: eight waves (9) on BF16 and FP16, four (2) on bf16x3.  With long
+    ranges the 256 x 256 split stays, and the 128 x 128 tile keeps its own
+    split against 64 x 64 tiles."""
+    for shape in ((2048, 2048, 1024), (1024, 4096, 1024)):
+        assert native.mg_tuned_config(1, *shape) == 2 and native.mg_split_count(1, *shape) == 1
+        for path in (2, 4):
+            assert native.mg_tuned_config(path, *shape) == 9 and native.mg_split_count(path, *shape) == 1
+    assert native.mg_tuned_config(1, 2048, 2048, 8192) == 1 and native.mg_split_count(1, 2048, 2048, 8192) == 4
+    assert native.mg_tuned_config(1, 1024, 1024, 1024) == 2 and native.mg_split_count(1, 1024, 1024, 1024) == 4
 
 
 def test_sixteen_bit_split_rule(rule):
