@@ -217,6 +217,9 @@ const SgemmConfig kBf16Configs[] = {
     // 32 x 64 each): two waves per SIMD
     {8, 128, 128, 32, 64, 32},
     {9, 128, 128, 32, 32, 64},
+    // configuration 7's panels copied straight into LDS, over eight 64 x 32
+    // waves; without the planes it runs as configuration 8
+    {10, 128, 128, 64, 64, 32},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
@@ -238,6 +241,9 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
         return launch_bf16_cfg<128, 128, 32, 64, 64, TERMS>(ta, tb, g, stream, packed);
     case 8: return launch_bf16_cfg<128, 128, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
     case 9: return launch_bf16_cfg<128, 128, 32, 32, 64, TERMS>(ta, tb, g, stream, packed);
+    case 10:
+        if (packed) return launch_bf16_direct<128, 128, 64, 32, TERMS>(g, stream);
+        return launch_bf16_cfg<128, 128, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }

@@ -247,16 +247,21 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // M N >= 1250 (M + N) for bf16x3.
             const int s16 = split_ok ? splits_16bit(n, K, cus) : 1;
             if (n * s16 * 2 < cus) continue;
-            // as for FP32 below: the 256 x 256 tile, when it needs K ranges
-            // as short as kMinRange, gives way to the 128 x 128 tile if that
-            // one fills the GPU unsplit (NN, beta 0.5, us: 2048 x 2048 x 1024
-            // bf16x3 51.4 -> 46.5, BF16 44.5 -> 26.9; 1024 x 4096 x 1024
-            // bf16x3 51.3 -> 47.0, BF16 46.1 -> 28.0).  The 128 x 128 tile
-            // keeps its split against the 64 x 64 one (bf16x3 1024^3: 25.0 us
-            // in four K ranges, 32.0 us unsplit on 64 x 64 tiles).
-            if (i == 0 && s16 > 1 && K / s16 <= kMinRange &&
+            // The 256 x 256 tile, when it needs a K split, gives way to the
+            // 128 x 128 tile if that one fills the GPU unsplit: on pre-packed
+            // planes as eight waves fed by direct copies (10), else in its
+            // in-kernel form.  Measured (NN, beta 0.5, us, 256 x 256 split
+            // -> 10 unsplit): BF16 4096 x 2048 x 2048 74.9 -> 55.6, 2560^3
+            // 72.3 -> 56.6, 2048 x 2048 x 8192 119.9 -> 111.5; bf16x3 2048^3
+            // 73.8 -> 67.3, 2048 x 2048 x 1024 51.4 -> 40.7, 4096 x 2048 x
+            // 2048 122.8 -> 109.4, 2560^3 120.3 -> 115.3.  bf16x3 keeps the
+            // split for K ranges of 2048 and more (2048 x 2048 x 8192: 213.4
+            // against 237.5).  The 128 x 128 tile itself keeps its split
+            // against the 64 x 64 one (bf16x3 1024^3: 25.0 us in four K
+            // ranges, 32.0 us unsplit on 64 x 64 tiles).
+            if (i == 0 && s16 > 1 && (path != MG_PATH_BF16X3 || K / s16 < 2048) &&
                 tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn) >= cus)
-                return ladder[1];
+                return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
             if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
                 (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
                 return 6;
@@ -473,13 +478,13 @@ bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 }
 
 // Whether configuration `cfg` of a 16-bit path multiplies pre-packed planes.
-// bf16x3 packs only for its direct form (6), into interleaved planes: with
+// bf16x3 packs only for its direct forms (6, 7, 10), into interleaved planes: with
 // the in-kernel conversion its packed operands would be as large as the
 // FP32 ones for no gain (about 347 against 370 TFLOP/s at 8192^3).
 bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K)
 {
     if (path == MG_PATH_BF16X3)
-        return (cfg == 6 || cfg == 7) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+        return (cfg == 6 || cfg == 7 || cfg == 10) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
     return bf16_prepack_pays(path, M, N, K);
 }
 

@@ -105,7 +105,7 @@ def test_ragged_shapes_all_layouts(gpu, path, tA, tB, M, N, K):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", list(range(10)))
+@pytest.mark.parametrize("cfg", list(range(11)))
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, path, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, path, cfg=cfg)
@@ -123,7 +123,7 @@ def test_prepacked_and_in_kernel_conversion(gpu, path, tA, tB, use_workspace):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", list(range(10)))
+@pytest.mark.parametrize("cfg", list(range(11)))
 def test_prepacked_every_config(gpu, path, cfg):
     _check(Problem(777, 531, 203, "T", "N", -1.0, 0.25, seed=100 + cfg), gpu, path, cfg=cfg)
 
@@ -133,15 +133,17 @@ def test_prepacked_every_config(gpu, path, cfg):
 @pytest.mark.parametrize("use_workspace", [True, False])
 def test_eight_wave_tiles_bit_identical(gpu, path, tA, tB, use_workspace):
     """Configurations 8 and 9 run configuration 2's 128 x 128 tile over eight
-    waves (64 x 32, 32 x 64) instead of four 64 x 64 ones: every output still
-    accumulates its k in the same order, so the bits are the same, on
-    pre-packed planes and with the conversion in the GEMM."""
+    waves (64 x 32, 32 x 64) instead of four 64 x 64 ones, and 10 does the
+    same for the direct-copy tile 7: every output still accumulates its k in
+    the same order, so the bits are the same, on pre-packed planes and with
+    the conversion in the GEMM (where 7 and 10 run as 2 and 8)."""
     outs = []
-    for cfg in (2, 8, 9):
+    for cfg in (2, 8, 9, 7, 10):
         C, _, _ = _check(Problem(600, 530, 300, tA, tB, 1.5, 0.5, seed=7 + ord(tA)), gpu, path, cfg=cfg,
                          use_workspace=use_workspace)
         outs.append(C)
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for C in outs[1:]:
+        assert np.array_equal(outs[0], C)
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])

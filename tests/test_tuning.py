@@ -194,7 +194,8 @@ def test_sixteen_bit_direct_copy_choice(rule):
         assert native.mg_tuned_config(path, 256, 8192, 8192) == 1          # M < 512: no planes
         assert native.mg_tuned_config(path, 8192, 8192, 2 ** 21 + 1) == 1  # beyond the planes' K limit
     # bf16x3 pre-splits only where both operands are re-read often enough
-    assert native.mg_tuned_config(1, 2048, 2048, 2048) == 1
+    # (or for the 128 x 128 direct tile, which 2048^3 takes unsplit)
+    assert native.mg_tuned_config(1, 2048, 2048, 2048) == 10
     assert native.mg_tuned_config(1, 16384, 1024, 4096) == 1
     assert native.mg_tuned_config(1, 4096, 4096, 4096) == 6
     assert native.mg_tuned_config(1, 2048, 8192, 2048) == 6
@@ -248,33 +249,47 @@ def test_fp32_model_of_the_eight_wave_tile(rule):
     assert native.mg_tuned_config(0, 2048, 2048, 2048) == 18
 
 
-def test_sixteen_bit_ladder_steps_down_from_short_k_ranges(rule):
+def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
     native = rule
-    """Where 256 x 256 tiles would need 256-deep K ranges and unsplit 128 x 128
-    tiles fill the compute units, the 16-bit rule takes the 128 x 128 tile
-    unsplit: eight waves (9) on BF16 and FP16, four (2) on bf16x3.  With long
-    ranges the 256 x 256 split stays, and the 128 x 128 tile keeps its own
-    split against 64 x 64 tiles."""
-    for shape in ((2048, 2048, 1024), (1024, 4096, 1024)):
-        assert native.mg_tuned_config(1, *shape) == 2 and native.mg_split_count(1, *shape) == 1
-        for path in (2, 4):
-            assert native.mg_tuned_config(path, *shape) == 9 and native.mg_split_count(path, *shape) == 1
+    """Where 256 x 256 tiles would need a K split and unsplit 128 x 128 tiles
+    fill the compute units, the 16-bit rule takes the 128 x 128 tile unsplit:
+    on pre-packed planes as eight waves fed by direct copies (10).  bf16x3
+    keeps the split for K ranges of 2048 or more; whole rounds of 256 x 256
+    tiles stay; the 128 x 128 tile keeps its own split against 64 x 64 tiles;
+    without pre-packed planes (M below 512) the in-kernel forms run."""
+    for shape in ((2048, 2048, 1024), (1024, 4096, 1024), (2048, 2048, 2048), (4096, 2048, 2048),
+                  (2560, 2560, 2560)):
+        for path in (1, 2, 4):
+            assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (10, 1), \
+                (path, shape)
+    for path in (2, 4):
+        assert native.mg_tuned_config(path, 2048, 2048, 8192) == 10
     assert native.mg_tuned_config(1, 2048, 2048, 8192) == 1 and native.mg_split_count(1, 2048, 2048, 8192) == 4
+    for path in (1, 2, 4):
+        assert native.mg_tuned_config(path, 3072, 3072, 3072) == 6
     assert native.mg_tuned_config(1, 1024, 1024, 1024) == 2 and native.mg_split_count(1, 1024, 1024, 1024) == 4
+    # 256 rows: no planes; 128 x 128 tiles (2 x 64 = 128) do not fill the
+    # compute units, so the ladder's split stays
+    assert native.mg_tuned_config(2, 256, 8192, 8192) == 1
 
 
 def test_sixteen_bit_split_rule(rule):
     native = rule
     """16-bit paths split K into as many ranges as fit one round of
-    workgroups (rounded down)."""
+    workgroups (rounded down), unless unsplit 128 x 128 tiles fill the
+    compute units (then those run, see the step-down test)."""
     for path in (1, 2, 4):
         assert native.mg_split_count(path, 3072, 3072, 3072) == 1     # 144 tiles of 256 x 256
         assert native.mg_split_count(path, 3072, 3072, 1024) == 1
-        assert native.mg_split_count(path, 2560, 2560, 2560) == 2     # 100 tiles: 200 workgroups
+        assert native.mg_split_count(path, 2560, 2560, 2560) == 1     # 400 tiles of 128 x 128
         assert native.mg_split_count(path, 1536, 1536, 4096) == 7     # 36 tiles: 252 workgroups
-        assert native.mg_split_count(path, 2048, 2048, 2048) == 4     # 64 tiles: 256 workgroups
+        assert native.mg_split_count(path, 2048, 2048, 2048) == 1     # 256 tiles of 128 x 128
         assert native.mg_split_count(path, 8192, 8192, 8192) == 1
-        assert native.mg_split_count(path, 4096, 2048, 8192) == 2     # 128 tiles: 256 workgroups
+    # 128 tiles of 256 x 256 in two ranges; BF16 and FP16 take 512 unsplit
+    # 128 x 128 tiles instead, bf16x3 keeps 4096-deep ranges
+    assert native.mg_split_count(1, 4096, 2048, 8192) == 2
+    for path in (2, 4):
+        assert native.mg_split_count(path, 4096, 2048, 8192) == 1
 
 
 def test_fp8_big_tile_threshold(rule):
