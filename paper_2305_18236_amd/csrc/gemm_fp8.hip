@@ -555,6 +555,7 @@ const SgemmConfig kFp8Configs[] = {
     {7, 256, 256, 128, 128, 64},   // panels copied straight into LDS
     {8, 128, 128, 128, 64, 64},    // panels copied straight into LDS
     {9, 128, 128, 128, 64, 64},    // as 8, barrier before each panel's last step
+    {10, 128, 128, 128, 64, 32},   // as 8 over eight 64 x 32 waves
 };
 const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
 
@@ -571,6 +572,7 @@ hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
     case 7: return launch_fp8_direct<256, 256, 128, 64, false>(g, stream);
     case 8: return launch_fp8_direct<128, 128, 64, 64, false>(g, stream);
     case 9: return launch_fp8_direct<128, 128, 64, 64, true>(g, stream);
+    case 10: return launch_fp8_direct<128, 128, 64, 32, false>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

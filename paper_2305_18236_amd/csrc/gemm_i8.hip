@@ -392,6 +392,7 @@ const SgemmConfig kI8Configs[] = {
     {3, 256, 256, 128, 128, 64},   // packs interleaved with the matrix work
     {4, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
     {5, 256, 256, 128, 128, 64},   // panels copied straight into LDS
+    {6, 128, 128, 128, 64, 32},    // panels copied straight into LDS, eight 64 x 32 waves
 };
 const int kNumI8Configs = sizeof(kI8Configs) / sizeof(kI8Configs[0]);
 
@@ -404,6 +405,7 @@ hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream)
     case 3: return launch_i8_cfg<256, 256, 128, 64, true>(g, stream);
     case 4: return launch_i8_cfg<128, 128, 64, 64, true>(g, stream);
     case 5: return launch_i8_direct<256, 256, 128, 64>(g, stream);
+    case 6: return launch_i8_direct<128, 128, 64, 32>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -396,9 +396,13 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // the direct copy (8), 1904-1954 vs 1764-1839.  The big tile wins as
         // soon as its tiles keep more than half the compute units busy
         // (3072^3, 144 tiles: 45.7 us against 48.8 us; 2560^3, 100 tiles:
-        // 128 x 128 is best, 28.5 us).
+        // 128 x 128 is best, 28.5 us).  The 128 x 128 tile runs as eight
+        // 64 x 32 waves fed by direct copies (10), bit-identical to 8 and
+        // faster than the interleaved pack (GEMM only, us, 6 -> 10: 2048^3
+        // 17.7 -> 14.8, 2560^3 27.1 -> 25.0, 4096 x 2048 x 2048 24.6 -> 22.3,
+        // 1536^3 14.1 -> 11.4).
         if (tiles(M, N, 256, 256) * 2 > cus) return 7;
-        if (tiles(M, N, 128, 128) >= 128) return 6;
+        if (tiles(M, N, 128, 128) >= 128) return 10;
         return 3;
     }
     if (path == MG_CONFIGS_I8) {
@@ -407,9 +411,12 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // the plain loop (0); 128 x 128: the interleaved pack (4).  As for
         // FP8, the big tile from more than half the compute units' worth of
         // tiles on (3072^3, 144 tiles: 47.5 us against 54.1 us; 4096 x 2048 x
-        // 8192, 128 tiles: 81.2 us for 128 x 128 against 100.6 us)
+        // 8192, 128 tiles: 81.2 us for 128 x 128 against 100.6 us).  The
+        // 128 x 128 tile runs as eight 64 x 32 waves fed by direct copies
+        // (6): GEMM only, us, 4 -> 6: 2048^3 16.9 -> 14.6, 2560^3 27.3 ->
+        // 22.9, 4096 x 2048 x 2048 25.5 -> 22.4
         if (tiles(M, N, 256, 256) * 2 > cus) return 5;
-        if (tiles(M, N, 128, 128) >= 128) return 4;
+        if (tiles(M, N, 128, 128) >= 128) return 6;
         return 2;
     }
     // Tiny FP32 products: no packing (the Tiling strategy) is fastest, as the
