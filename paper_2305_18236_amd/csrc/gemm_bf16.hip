@@ -220,6 +220,9 @@ const SgemmConfig kBf16Configs[] = {
     // configuration 7's panels copied straight into LDS, over eight 64 x 32
     // waves; without the planes it runs as configuration 8
     {10, 128, 128, 64, 64, 32},
+    // configuration 6 over sixteen 64 x 64 waves; without the planes it runs
+    // as configuration 1
+    {11, 256, 256, 64, 64, 64},
 };
 const int kNumBf16Configs = sizeof(kBf16Configs) / sizeof(kBf16Configs[0]);
 
@@ -244,6 +247,9 @@ static hipError_t launch_terms(int cfg, bool ta, bool tb, GemmArgs g, hipStream_
     case 10:
         if (packed) return launch_bf16_direct<128, 128, 64, 32, TERMS>(g, stream);
         return launch_bf16_cfg<128, 128, 32, 64, 32, TERMS>(ta, tb, g, stream, packed);
+    case 11:
+        if (packed) return launch_bf16_direct<256, 256, 64, 64, TERMS>(g, stream);
+        return launch_bf16_cfg<256, 256, 32, 128, 64, TERMS>(ta, tb, g, stream, packed);
     default: return hipErrorInvalidValue;
     }
 }

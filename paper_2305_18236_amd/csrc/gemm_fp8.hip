@@ -556,6 +556,7 @@ const SgemmConfig kFp8Configs[] = {
     {8, 128, 128, 128, 64, 64},    // panels copied straight into LDS
     {9, 128, 128, 128, 64, 64},    // as 8, barrier before each panel's last step
     {10, 128, 128, 128, 64, 32},   // as 8 over eight 64 x 32 waves
+    {11, 256, 256, 128, 64, 64},   // as 7 over sixteen 64 x 64 waves
 };
 const int kNumFp8Configs = sizeof(kFp8Configs) / sizeof(kFp8Configs[0]);
 
@@ -573,6 +574,7 @@ hipError_t launch_gemm_fp8(int cfg, Fp8Args g, hipStream_t stream)
     case 8: return launch_fp8_direct<128, 128, 64, 64, false>(g, stream);
     case 9: return launch_fp8_direct<128, 128, 64, 64, true>(g, stream);
     case 10: return launch_fp8_direct<128, 128, 64, 32, false>(g, stream);
+    case 11: return launch_fp8_direct<256, 256, 64, 64, false>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

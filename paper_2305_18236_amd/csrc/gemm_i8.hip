@@ -393,6 +393,7 @@ const SgemmConfig kI8Configs[] = {
     {4, 128, 128, 128, 64, 64},    // packs interleaved with the matrix work
     {5, 256, 256, 128, 128, 64},   // panels copied straight into LDS
     {6, 128, 128, 128, 64, 32},    // panels copied straight into LDS, eight 64 x 32 waves
+    {7, 256, 256, 128, 64, 64},    // as 5 over sixteen 64 x 64 waves
 };
 const int kNumI8Configs = sizeof(kI8Configs) / sizeof(kI8Configs[0]);
 
@@ -406,6 +407,7 @@ hipError_t launch_gemm_i8(int cfg, I8Args g, hipStream_t stream)
     case 4: return launch_i8_cfg<128, 128, 64, 64, true>(g, stream);
     case 5: return launch_i8_direct<256, 256, 128, 64>(g, stream);
     case 6: return launch_i8_direct<128, 128, 64, 32>(g, stream);
+    case 7: return launch_i8_direct<256, 256, 64, 64>(g, stream);
     default: return hipErrorInvalidValue;
     }
 }

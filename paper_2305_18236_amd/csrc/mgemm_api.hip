@@ -262,9 +262,14 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             if (i == 0 && s16 > 1 && (path != MG_PATH_BF16X3 || K / s16 < 2048) &&
                 tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn) >= cus)
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
+            // BF16 and FP16 run that tile over sixteen 64 x 64 waves (11,
+            // four per SIMD, bit-identical to 6): end to end, us, 6 -> 11:
+            // BF16 8192^3 1030.1 -> 1008.0, 6144^3 540.1 -> 519.4, 4096^3
+            // 142.3 -> 141.0; FP16 8192^3 1066.6 -> 1037.5.  bf16x3 keeps
+            // eight (8192^3 2454 against 2482 with sixteen).
             if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
                 (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
-                return 6;
+                return path == MG_PATH_BF16X3 ? 6 : 11;
             return ladder[i];
         }
         const int s = split_ok ? auto_splits(n, K) : 1;
@@ -415,7 +420,10 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // 128 x 128 tile runs as eight 64 x 32 waves fed by direct copies
         // (6): GEMM only, us, 4 -> 6: 2048^3 16.9 -> 14.6, 2560^3 27.3 ->
         // 22.9, 4096 x 2048 x 2048 25.5 -> 22.4
-        if (tiles(M, N, 256, 256) * 2 > cus) return 5;
+        // The 256 x 256 tile runs over sixteen 64 x 64 waves (7): GEMM only,
+        // us, 5 -> 7: 8192^3 479.6 -> 473.0, 6144^3 245.9 -> 236.2, 4096^3
+        // 66.6 -> 65.8.
+        if (tiles(M, N, 256, 256) * 2 > cus) return 7;
         if (tiles(M, N, 128, 128) >= 128) return 6;
         return 2;
     }
@@ -491,7 +499,8 @@ bool bf16_prepack_pays(int path, int64_t M, int64_t N, int64_t K)
 bool uses_planes(int path, int cfg, int64_t M, int64_t N, int64_t K)
 {
     if (path == MG_PATH_BF16X3)
-        return (cfg == 6 || cfg == 7 || cfg == 10) && M >= 512 && N >= 512 && K >= 32 && K <= kMaxPrepackK;
+        return (cfg == 6 || cfg == 7 || cfg == 10 || cfg == 11) && M >= 512 && N >= 512 && K >= 32 &&
+               K <= kMaxPrepackK;
     return bf16_prepack_pays(path, M, N, K);
 }
 

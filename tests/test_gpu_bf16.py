@@ -105,7 +105,7 @@ def test_ragged_shapes_all_layouts(gpu, path, tA, tB, M, N, K):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", list(range(11)))
+@pytest.mark.parametrize("cfg", list(range(12)))
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, path, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, path, cfg=cfg)
@@ -123,7 +123,7 @@ def test_prepacked_and_in_kernel_conversion(gpu, path, tA, tB, use_workspace):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("cfg", list(range(11)))
+@pytest.mark.parametrize("cfg", list(range(12)))
 def test_prepacked_every_config(gpu, path, cfg):
     _check(Problem(777, 531, 203, "T", "N", -1.0, 0.25, seed=100 + cfg), gpu, path, cfg=cfg)
 
@@ -144,6 +144,20 @@ def test_eight_wave_tiles_bit_identical(gpu, path, tA, tB, use_workspace):
         outs.append(C)
     for C in outs[1:]:
         assert np.array_equal(outs[0], C)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("use_workspace", [True, False])
+def test_sixteen_wave_tile_bit_identical(gpu, path, use_workspace):
+    """Configuration 11 runs configuration 6's 256 x 256 direct-copy tile over
+    sixteen 64 x 64 waves: the same products in the same order per output,
+    so the same bits (without the planes both run as configuration 1)."""
+    outs = []
+    for cfg in (6, 11):
+        C, _, _ = _check(Problem(600, 530, 300, "N", "T", 1.5, 0.5, seed=23), gpu, path, cfg=cfg,
+                         use_workspace=use_workspace)
+        outs.append(C)
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])

@@ -57,7 +57,7 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + 7 * N + 13 * K + 5), gpu)
 
 
-@pytest.mark.parametrize("cfg", list(range(11)))
+@pytest.mark.parametrize("cfg", list(range(12)))
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     _check(Problem(530, 390, 77, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 5 + ord(tB)), gpu, cfg=cfg)

@@ -128,13 +128,13 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(Problem(M, N, K, tA, tB, 1.5, 0.5, seed=M + 7 * N + 13 * K), gpu)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     _check(Problem(530, 390, 300, tA, tB, -1.25, 0.75, seed=cfg + ord(tA) * 3 + ord(tB)), gpu, cfg=cfg)
 
 
-@pytest.mark.parametrize("cfg", [5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("cfg", [5, 6, 7, 8, 9, 10, 11])
 @pytest.mark.parametrize("K", [1, 128, 129, 256, 384, 1000])
 def test_interleaved_pack_panel_counts(gpu, cfg, K):
     """The two-buffer loops (interleaved staging, direct copies) and their
@@ -151,6 +151,8 @@ def test_eight_wave_direct_tile_bit_identical(gpu, tA, tB):
     C8 = _check(p, gpu, cfg=8)[0]
     C10 = _check(p, gpu, cfg=10)[0]
     assert np.array_equal(C8, C10)
+    # and configuration 11 runs 7's 256 x 256 tile over sixteen 64 x 64 waves
+    assert np.array_equal(_check(p, gpu, cfg=7)[0], _check(p, gpu, cfg=11)[0])
 
 
 def test_log_uniform_magnitudes(gpu):

@@ -77,14 +77,14 @@ def test_bit_exact_ragged_all_layouts(gpu, tA, tB, M, N, K):
     assert np.array_equal(p.run(gpu), p.oracle())
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     p = I8Problem(530, 390, 300, tA, tB, alpha=-1, beta=1, seed=cfg + 3 * ord(tA) + ord(tB))
     assert np.array_equal(p.run(gpu, cfg=cfg), p.oracle())
 
 
-@pytest.mark.parametrize("cfg", [3, 4, 5, 6])
+@pytest.mark.parametrize("cfg", [3, 4, 5, 6, 7])
 @pytest.mark.parametrize("K", [1, 128, 129, 256, 384, 1000])
 def test_interleaved_pack_panel_counts(gpu, cfg, K):
     """The two-staging-set loop at every parity of the panel count (1, 2, 3
