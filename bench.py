@@ -89,6 +89,15 @@ def measured_traffic(profile=PROFILE_TRAFFIC):
         return None
 
 
+def tuned_kernel_name(native, path, kernel, M, N, K):
+    """`kernel<BM,BN,WM,WN> (configuration c)` for the configuration the
+    library picks for an M x N x K GEMM on `path` (the direct-copy kernels'
+    template arguments)."""
+    cfg = native.mg_tuned_config(path, M, N, K)
+    c = native.mg_config_info(path, cfg)
+    return f"{kernel}<{c['bm']},{c['bn']},{c['wm']},{c['wn']}> (configuration {cfg})"
+
+
 def native_plan_config(bench, M, N, K):
     """The FP32 configuration mg_gemm runs for an M x N x K problem (no workspace)."""
     st, cfg, _, _ = bench.native.mg_gemm_plan(PATH_ID["fp32"], M, N, K, 0)
@@ -660,7 +669,8 @@ def bench_mixed(bench, si):
     fo = u["fp8_gemm_only"]
     out["roofline"] = {"bound": "mfma", "achieved": fo["tflops"], "peak": PEAK_TFLOPS["fp8"], "unit": "TFLOP/s",
                        "frac": round(fo["tflops"] / PEAK_TFLOPS["fp8"], 4), "traffic": None,
-                       "kernel": "gemm_fp8_direct_kernel<256,256,128,64> (FP8 GEMM on packed operands)",
+                       "kernel": tuned_kernel_name(bench.native, 3, "gemm_fp8_direct_kernel", M, N, K)
+                       + ", FP8 GEMM on packed operands",
                        "kernel_ms_mean": fo["ms"], "algorithmic_flops_per_launch": flops}
     out["rows"] = rows
     return out
@@ -1094,7 +1104,7 @@ def bench_types(bench, si):
                   "int8_inputs": "uniform integers in [-128, 127]", "rounds": args.rounds})
     out["roofline"] = {"bound": "mfma", "achieved": g["tops"], "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                        "frac": g["frac_of_int8_peak"], "traffic": None,
-                       "kernel": "gemm_i8_direct_kernel<256,256,128,64>"}
+                       "kernel": tuned_kernel_name(native, 5, "gemm_i8_direct_kernel", n, n, n)}
     out["rows"] = rows
     return out
 
