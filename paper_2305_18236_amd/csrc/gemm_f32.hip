@@ -68,6 +68,8 @@ const SgemmConfig kSgemmConfigs[] = {
     // 14 (four 64 x 64 waves) have one
     {18, 128, 128, 32, 64, 32},
     {19, 128, 128, 32, 32, 64},
+    // the 128 x 64 tile over eight 32 x 32 waves with two staging sets
+    {20, 128, 64, 32, 32, 32},
 };
 const int kNumSgemmConfigs = sizeof(kSgemmConfigs) / sizeof(kSgemmConfigs[0]);
 
@@ -94,6 +96,7 @@ hipError_t launch_sgemm(int cfg, bool ta, bool tb, GemmArgs g, hipStream_t strea
     case 17: return launch_sgemm_cfg<256, 256, 16, 128, 64, true>(ta, tb, g, stream);
     case 18: return launch_sgemm_cfg<128, 128, 32, 64, 32, true>(ta, tb, g, stream);
     case 19: return launch_sgemm_cfg<128, 128, 32, 32, 64, true>(ta, tb, g, stream);
+    case 20: return launch_sgemm_cfg<128, 64, 32, 32, 32, true>(ta, tb, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

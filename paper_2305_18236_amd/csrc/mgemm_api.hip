@@ -380,10 +380,17 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 // with the same K ranges (NN, beta 0.5, us): 1024 x 4096 x 1024 94.7 ->
 // 75.4, 512 x 2048 x 2048 in four ranges 53.9 -> 46.3, 3072 x 4096 x 4096
 // 869 -> 821, 1792 x 1536 x 4096 in three ranges 211.5 -> 203.6.
+// The 128 x 64 tile of short K loops runs over eight 32 x 32 waves with two
+// staging sets (20), in every layout faster than configuration 4 (% of the
+// FP32 peak, NN / NT / TN / TT): 8192 x 8192 x 256 62.1 / 62.4 / 61.3 / 61.4
+// -> 64.3 / 64.4 / 63.0 / 63.4, 8192 x 8192 x 512 69.1 / 69.1 / 69.1 / 68.7
+// -> 72.3 / 72.7 / 71.0 / 72.1, 4096 x 4096 x 256 59.5 / 59.1 / 59.6 /
+// 59.4 -> 62.5 / 62.8 / 61.6 / 62.1.
 int fp32_small_tile(int cfg, int64_t M, int64_t N, int64_t K, int splits, bool split_ok)
 {
     if (cfg == 5) return 17;
     if (cfg == 0) return 18;
+    if (cfg == 4) return 20;
     if (cfg != 3) return cfg;
     const int64_t cus = device_cus();
     const int64_t t = tiles(M, N, 64, 64);
@@ -547,7 +554,7 @@ SplitPlan split_plan(int path, int cfg, int64_t M, int64_t N, int64_t K, bool sp
         // the K ranges the round plan chose with this configuration
         const Fp32Plan fp = fp32_plan(M, N, K, ladder_choice(path, M, N, K, device_cus(), true), true);
         if (fp.cfg == cfg || (fp.cfg == 3 && (cfg == 12 || cfg == 15)) || (fp.cfg == 5 && cfg == 17) ||
-            (fp.cfg == 0 && cfg == 18))
+            (fp.cfg == 0 && cfg == 18) || (fp.cfg == 4 && cfg == 20))
             s = fp.splits;
     }
     if (s < 0) s = path == MG_PATH_FP32 ? auto_splits(tiles(M, N, c.bm, c.bn), K)

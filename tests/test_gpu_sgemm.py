@@ -55,7 +55,7 @@ def test_ragged_shapes_all_layouts(gpu, tA, tB, M, N, K):
     _check(p, gpu)
 
 
-@pytest.mark.parametrize("cfg", list(range(20)))
+@pytest.mark.parametrize("cfg", list(range(21)))
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_every_config_every_layout(gpu, cfg, tA, tB):
     """Each tile configuration over several tiles and a ragged tail (8 and 9
@@ -64,15 +64,16 @@ def test_every_config_every_layout(gpu, cfg, tA, tB):
     _check(p, gpu, cfg=cfg)
 
 
-@pytest.mark.parametrize("deep,single", [(12, 3), (13, 4), (14, 0), (17, 5), (18, 0), (19, 0)])
+@pytest.mark.parametrize("deep,single", [(12, 3), (13, 4), (14, 0), (17, 5), (18, 0), (19, 0), (20, 4)])
 @pytest.mark.parametrize("tA,tB", LAYOUTS)
 def test_two_staging_sets_bit_identical(gpu, deep, single, tA, tB):
     """Configurations 12-14 and 17 are 3, 4, 0 and 5 with each panel fetched a panel
     earlier into a second register staging set: the same products in the
     same order, so the same bits (odd and even panel counts, ragged edges).
     18 and 19 split configuration 0's 128 x 128 tile over eight waves
-    instead of four; each output still accumulates its k in the same order,
-    so they match 0 bit for bit too."""
+    instead of four, and 20 configuration 4's 128 x 64 tile; each output
+    still accumulates its k in the same order, so they match bit for bit
+    too."""
     for K in (77, 160, 1000):
         C1, _, _ = _check(Problem(300, 260, K, tA, tB, 1.5, 0.5, seed=K + deep), gpu, cfg=single)
         C2, _, _ = _check(Problem(300, 260, K, tA, tB, 1.5, 0.5, seed=K + deep), gpu, cfg=deep)

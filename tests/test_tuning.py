@@ -222,7 +222,7 @@ def test_fp32_round_plan(rule):
     assert plan(2048, 2048, 2048) == (17, 4)
     assert plan(4096, 4096, 1024) == (17, 1)
     assert plan(256, 8192, 8192) == (17, 8)
-    assert plan(8192, 8192, 256) == (4, 1)
+    assert plan(8192, 8192, 256) == (20, 1)   # the 128 x 64 tile over eight waves
     # the 64 x 64 tile runs as its two-staging-set form (12), or with two K
     # groups (15) where its workgroups give each compute unit at most one
     assert plan(1024, 1024, 1024) == (15, 1)   # one workgroup per compute unit: two K groups
