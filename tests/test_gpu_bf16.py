@@ -161,6 +161,15 @@ def test_sixteen_wave_tile_bit_identical(gpu, path, use_workspace):
 
 
 @pytest.mark.parametrize("path", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("cfg", [6, 7, 10, 11])
+@pytest.mark.parametrize("K", [1, 64, 65, 128, 192, 1000])
+def test_direct_copy_panel_counts(gpu, path, cfg, K):
+    """The direct-copy tiles on pre-packed planes (M, N >= 512) at one, two,
+    three and many 128-byte panels and ragged K, against the oracle."""
+    _check(Problem(520, 530, K, "N", "N", 1.5, 0.5, seed=K + 13 * cfg), gpu, path, cfg=cfg)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "bf16"])
 def test_prepacked_integer_bit_exact_and_layout_invariant(gpu, path):
     outs = []
     for tA, tB in LAYOUTS:
