@@ -1226,14 +1226,17 @@ def bench_syr2k(bench, si):
     flops = 2.0 * n * n * k
     ms = float(np.mean(per["syr2k"]))
     tf = tflops(flops, ms)
-    auto_splits = need // (4 * n * n) if need else 1
+    st, plan_cfg, auto_splits = native.mg_syr2k_plan(0, n, k)
+    native.check(st, "mg_syr2k_plan")
+    info = native.mg_config_info(0, plan_cfg)
     out = header(bench, "SYR2K TFLOP/s (2*N^2*K useful flops) at N = K = 8192", "TFLOP/s", round(tf, 2),
                  round(ms, 4), "f32", {"workload": "ssyr2k_lower_n_8192x8192", "N": n, "K": k, "uplo": "L",
                                        "trans": "N", "alpha": ALPHA, "beta": BETA, "inputs": "uniform[-1,1]",
                                        "rounds": args.rounds})
     out["roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
                        "frac": round(tf / PEAK_TFLOPS["fp32"], 4), "traffic": None,
-                       "kernel": f"syr2k_kernel (config {native.mg_tuned_config(0, n, n, k)} tiles)"}
+                       "kernel": f"syr2k_kernel<{info['bm']},{info['bk']},{info['wm']},{info['wn']}> "
+                                 f"(configuration {plan_cfg}, split {auto_splits})"}
     out["step_ms"] = {c: stats(v) for c, v in per.items()}
     out["sclk_mhz"] = clk
     out["splits"] = int(auto_splits)

@@ -195,7 +195,7 @@ int mg_gemm_plan(int path, int64_t M, int64_t N, int64_t K, size_t workspace_byt
  * other strict triangle is never touched.  beta == 0: C is not read;
  * alpha == 0 or K == 0: the triangle becomes beta*C.  path: MG_PATH_FP32 (the
  * only one; others return MG_ERR_UNSUPPORTED).  A forced FP32 configuration
- * must be square (ids 0, 3, 5).  `workspace` (optional, device, 256-byte
+ * must be square (ids 0, 3, 5, 18).  `workspace` (optional, device, 256-byte
  * aligned, mg_syr2k_workspace_size() bytes) holds partial tiles when each
  * tile's K loop is split over several workgroups (so that the triangle's
  * tiles fill the GPU's last round); with NULL or too few bytes the update
@@ -207,6 +207,18 @@ int mg_syr2k(int path, char uplo, char trans, int64_t N, int64_t K, float alpha,
              const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
              float *C, int64_t ldc, void *workspace, size_t workspace_bytes, void *stream);
 size_t mg_syr2k_workspace_size(int path, int64_t N, int64_t K);
+
+/*
+ * The tiles mg_syr2k runs for this problem with the current selection state
+ * and a workspace of mg_syr2k_workspace_size() bytes: out2[0] = the square
+ * FP32 configuration id (mg_config_info), out2[1] = the number of ranges each
+ * tile's two-product K loop is cut into (1: no split); N == 0 or K == 0
+ * (no tile kernel runs) gives -1 and 0.  Host-only: no device
+ * call.  Errors: MG_ERR_UNSUPPORTED for a path other than MG_PATH_FP32 or a
+ * forced configuration that is not square, -3 N < 0, -4 K < 0, -5 out2
+ * NULL, MG_ERR_TOO_LARGE as mg_syr2k.
+ */
+int mg_syr2k_plan(int path, int64_t N, int64_t K, int *out2);
 
 /*
  * INT8 GEMM, the 8-bit integer operand type of the paper's Table 1:

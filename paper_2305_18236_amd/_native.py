@@ -90,6 +90,8 @@ def lib():
     L.mg_syr2k.restype = ci
     L.mg_syr2k_workspace_size.argtypes = [ci, i64, i64]
     L.mg_syr2k_workspace_size.restype = sz
+    L.mg_syr2k_plan.argtypes = [ci, i64, i64, ctypes.POINTER(ci)]
+    L.mg_syr2k_plan.restype = ci
     i32 = ctypes.c_int32
     L.mg_gemm_i8.argtypes = [ch, ch, i64, i64, i64, i32, vp, i64, vp, i64, i32, vp, i64, vp, sz, vp]
     L.mg_gemm_i8.restype = ci
@@ -200,6 +202,13 @@ def mg_syr2k(path, uplo, trans, N, K, alpha, A, lda, B, ldb, beta, C, ldc, works
 
 def mg_syr2k_workspace_size(path, N, K) -> int:
     return int(lib().mg_syr2k_workspace_size(int(path), N, K))
+
+
+def mg_syr2k_plan(path, N, K):
+    """(status, config, splits) of the tiles mg_syr2k would run."""
+    out = (ctypes.c_int * 2)()
+    st = int(lib().mg_syr2k_plan(int(path), N, K, out))
+    return st, int(out[0]), int(out[1])
 
 
 def mg_gemm_i8(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, workspace, workspace_bytes,

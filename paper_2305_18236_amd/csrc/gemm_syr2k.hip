@@ -84,7 +84,7 @@ static hipError_t launch_syr2k_cfg(bool lower, bool tr, int splits, GemmArgs g, 
     return hipGetLastError();
 }
 
-bool syr2k_config_supported(int cfg) { return cfg == 0 || cfg == 3 || cfg == 5; }
+bool syr2k_config_supported(int cfg) { return cfg == 0 || cfg == 3 || cfg == 5 || cfg == 18; }
 
 int syr2k_panel_depth(int cfg) { return cfg == 5 ? 16 : 32; }
 
@@ -94,6 +94,7 @@ hipError_t launch_syr2k(int cfg, bool lower, bool tr, int splits, GemmArgs g, hi
     case 0: return launch_syr2k_cfg<128, 32, 64, 64>(lower, tr, splits, g, stream);
     case 3: return launch_syr2k_cfg<64, 32, 32, 32>(lower, tr, splits, g, stream);
     case 5: return launch_syr2k_cfg<256, 16, 128, 64>(lower, tr, splits, g, stream);
+    case 18: return launch_syr2k_cfg<128, 32, 64, 32>(lower, tr, splits, g, stream);
     default: return hipErrorInvalidValue;
     }
 }

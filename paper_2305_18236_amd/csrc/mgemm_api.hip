@@ -829,7 +829,11 @@ Syr2kPlan syr2k_plan(int64_t N, int64_t K)
     auto tri = [&](int64_t b) { const int64_t t = (N + b - 1) / b; return t * (t + 1) / 2; };
     int cfg = g_forced[MG_PATH_FP32].load();
     if (cfg >= 0 && !mg::syr2k_config_supported(cfg)) return p;
-    if (cfg < 0) cfg = tri(256) >= cus ? 5 : tri(128) >= cus ? 0 : 3;
+    // 256 x 256 tiles once their triangle fills four rounds of the compute
+    // units; below that the eight-wave 128 x 128 tile, whose finer triangle
+    // splits into more even rounds; 64 x 64 only for triangles under half a
+    // round of 128 x 128 tiles.
+    if (cfg < 0) cfg = tri(256) >= 4 * cus ? 5 : 2 * tri(128) >= cus ? 18 : 3;
     p.cfg = cfg;
     const int bt = table_of(MG_PATH_FP32).cfgs[cfg].bm;
     const int bk = mg::syr2k_panel_depth(cfg);
@@ -1109,6 +1113,25 @@ size_t mg_syr2k_workspace_size(int path, int64_t N, int64_t K)
 {
     if (path != MG_PATH_FP32 || N <= 0 || K <= 0 || beyond_int(N, K, 0)) return 0;
     return syr2k_plan(N, K).bytes;
+}
+
+int mg_syr2k_plan(int path, int64_t N, int64_t K, int* out2)
+{
+    if (path != MG_PATH_FP32) return MG_ERR_UNSUPPORTED;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    if (out2 == nullptr) return -5;
+    if (N > INT_MAX || K > INT_MAX) return MG_ERR_TOO_LARGE;
+    if (N == 0 || K == 0) {   // no tile kernel runs
+        out2[0] = -1;
+        out2[1] = 0;
+        return MG_OK;
+    }
+    const Syr2kPlan plan = syr2k_plan(N, K);
+    if (plan.cfg < 0) return MG_ERR_UNSUPPORTED;
+    out2[0] = plan.cfg;
+    out2[1] = plan.splits;
+    return MG_OK;
 }
 
 size_t mg_gemm_i8_workspace_size(int64_t M, int64_t N, int64_t K)

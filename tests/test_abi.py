@@ -186,6 +186,37 @@ def test_syr2k_split_plan(native):
         native.mg_force_splits(0, -1)
 
 
+def test_syr2k_plan_tiles(native):
+    """The square tile SYR2K runs: 256 x 256 once that triangle fills four
+    rounds of the compute units, the eight-wave 128 x 128 tile below that,
+    64 x 64 for triangles under half a round of 128 x 128 tiles; the split
+    reported is the one the workspace size is made for."""
+    cus = 256   # no device here: the library plans for a full MI355X
+    tri = lambda n, b: ((n + b - 1) // b) * ((n + b - 1) // b + 1) // 2
+    for n, k in [(16384, 8192), (12288, 4096), (8192, 8192), (4096, 4096), (2816, 1024), (2048, 2048),
+                 (1024, 1024), (100, 1000)]:
+        st, cfg, splits = native.mg_syr2k_plan(0, n, k)
+        assert st == 0
+        want = 5 if tri(n, 256) >= 4 * cus else 18 if 2 * tri(n, 128) >= cus else 3
+        assert cfg == want, (n, k)
+        ws = native.mg_syr2k_workspace_size(0, n, k)
+        assert (splits > 1) == (ws > 0)
+        if splits > 1:
+            assert ws >= splits * n * n * 4
+    assert native.mg_syr2k_plan(0, 0, 5) == (0, -1, 0)
+    assert native.mg_syr2k_plan(0, 5, 0) == (0, -1, 0)
+    assert native.mg_syr2k_plan(1, 64, 64)[0] == -101   # MG_ERR_UNSUPPORTED
+    assert native.mg_syr2k_plan(0, -1, 64)[0] == -3
+    assert native.mg_syr2k_plan(0, 64, -1)[0] == -4
+    try:
+        assert native.mg_force_config(0, 18) == 0
+        assert native.mg_syr2k_plan(0, 100, 100)[1] == 18
+        assert native.mg_force_config(0, 2) == 0   # 256 x 128 is not square
+        assert native.mg_syr2k_plan(0, 100, 100)[0] == -101
+    finally:
+        native.mg_force_config(0, -1)
+
+
 def test_library_shares_torchs_hip_runtime():
     """Loading the library before anything else imports torch must not bring
     a second HIP runtime into the process (torch's and the system's share a

@@ -70,11 +70,23 @@ def test_ragged_all_variants(gpu, uplo, trans, N, K):
     assert oracle.normalized_error(C, ref, D) <= TOL
 
 
-@pytest.mark.parametrize("cfg", [0, 3, 5])
+@pytest.mark.parametrize("cfg", [0, 3, 5, 18])
 @pytest.mark.parametrize("uplo,trans", list(itertools.product("LU", "NT")))
 def test_every_square_config(gpu, cfg, uplo, trans):
     C, ref, D = _run(gpu, uplo, trans, 530, 77, -1.25, 0.75, seed=cfg + 7, ldc=533, cfg=cfg)
     assert oracle.normalized_error(C, ref, D) <= TOL
+
+
+@pytest.mark.parametrize("splits", [1, 3])
+@pytest.mark.parametrize("uplo,trans", [("L", "N"), ("U", "T")])
+def test_eight_wave_tile_bit_identical(gpu, splits, uplo, trans):
+    """The 128 x 128 tile over eight 64 x 32 waves (configuration 18) adds
+    every entry's products in the same order as the four-wave tile
+    (configuration 0): the results agree bit for bit."""
+    a = _run(gpu, uplo, trans, 390, 203, 1.5, -0.5, seed=97, ldc=395, cfg=0, splits=splits)
+    b = _run(gpu, uplo, trans, 390, 203, 1.5, -0.5, seed=97, ldc=395, cfg=18, splits=splits)
+    assert np.array_equal(a[0], b[0])
+    assert oracle.normalized_error(b[0], b[1], b[2]) <= TOL
 
 
 def test_non_square_config_rejected(gpu):
@@ -92,12 +104,13 @@ def test_integer_inputs_exact(gpu, uplo, trans):
     assert np.array_equal(C, ref)
 
 
+@pytest.mark.parametrize("cfg", [0, 18])
 @pytest.mark.parametrize("splits", [2, 3, 7, 16])
 @pytest.mark.parametrize("uplo,trans", list(itertools.product("LU", "NT")))
-def test_split_k_loop(gpu, splits, uplo, trans):
+def test_split_k_loop(gpu, cfg, splits, uplo, trans):
     """Each tile's K loop (both products) cut into ranges whose partial tiles
     a reduction sums: ragged K, so a range can straddle the two products."""
-    C, ref, D = _run(gpu, uplo, trans, 270, 333, 1.5, 0.5, seed=splits + 61, ldc=274, splits=splits, cfg=0)
+    C, ref, D = _run(gpu, uplo, trans, 270, 333, 1.5, 0.5, seed=splits + 61, ldc=274, splits=splits, cfg=cfg)
     assert oracle.normalized_error(C, ref, D) <= TOL
 
 
