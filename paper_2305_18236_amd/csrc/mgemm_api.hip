@@ -341,6 +341,17 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
     const int64_t s0 = split_ok ? effective_splits(K, auto_splits(tiles(M, N, bm, bm), K)) : 1;
     const int64_t n = tiles(M, N, bm, bm) * s0;
     const int64_t rounds = (n + cus - 1) / cus;
+    // Where the big tile would split K and the 64 x 64 tiles unsplit already
+    // give every compute unit one or two workgroups, those win up to K = 4096
+    // (two workgroups per unit with two K groups each, configuration 15; us,
+    // NN, plan -> 64 x 64 unsplit): 1024 x 2048 x 1024 in two ranges of 128 x
+    // 128 tiles 47.2 -> 43.6, 2048 x 1024 x 2048 in eight ranges of 256 x 256
+    // 93.5 -> 79.0, 512 x 4096 x 2048 93.9 -> 78.6, 1024 x 1024 x 4096 in
+    // sixteen 93.2 -> 85.0, 512 x 2048 x 2048 in four of 128 x 128 46.6 ->
+    // 45.6; TT alike.  At K = 8192 the many short ranges of the big tile stay
+    // faster (1024 x 2048 x 8192: 277.7 against 294.9).
+    const int64_t t64 = tiles(M, N, 64, 64);
+    if (s0 > 1 && K <= 4096 && t64 >= cus && t64 <= 2 * cus) return Fp32Plan{3, 1};
     if (n * 10 >= rounds * cus * 8) return keep;   // last round at least 80 % full
     Fp32Plan best = keep;
     double best_t = 0.95 * fp32_model_us(pick, M, N, K, s0, cus);
@@ -369,8 +380,13 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
 // 55.7 -> 56.4, 3072^3 71.2 -> 74.3.  When its workgroups (tiles times K
 // ranges) give each compute unit at most one, the form with two K groups of
 // waves (15) takes it instead, two waves per SIMD where the others have
-// one: 1024^3 50.9 -> 54.3 (at 2048^3 and 3072^3, several workgroups per
-// compute unit, the two tie).
+// one: 1024^3 50.9 -> 54.3.  So it does at two workgroups per compute unit
+// when each K range is at least 512 long (us, 12 -> 15: 1024 x 2048 x 1024
+// 44.3 -> 43.6, 2048 x 1024 x 2048 82.0 -> 79.0, 640 x 3072 x 8192 307.9 ->
+// 292.5, 640 x 1536 x 4096 in two ranges 84.9 -> 81.8; at 512 they tie);
+// shorter ranges leave each K group too few panels (1536 x 768 x 128 9.9 ->
+// 10.5, 512 x 2560 x 256 15.0 -> 15.3).  At 3072^3, several workgroups per
+// compute unit, the two tie.
 // Likewise the 256 x 256 tile runs as its two-staging-set form (17):
 // measured against configuration 5 (% of the FP32 peak, same box, three
 // shuffled rounds): 8192^3 85.8 -> 88.2, 4096^3 84.5 -> 86.5,
@@ -395,7 +411,7 @@ int fp32_small_tile(int cfg, int64_t M, int64_t N, int64_t K, int splits, bool s
     const int64_t cus = device_cus();
     const int64_t t = tiles(M, N, 64, 64);
     const int64_t s = splits > 0 ? effective_splits(K, splits) : (split_ok ? effective_splits(K, auto_splits(t, K)) : 1);
-    return t * s <= cus ? 15 : 12;
+    return t * s <= cus || (t * s <= 2 * cus && (K + s - 1) / s >= 512) ? 15 : 12;
 }
 
 int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)

@@ -235,8 +235,24 @@ def test_fp32_round_plan(rule):
     # the 128 x 128 tile runs as eight waves with two staging sets (18)
     assert plan(1024, 4096, 1024) == (18, 1)
     assert plan(2048, 2048, 1024) == (18, 1)
-    assert plan(512, 2048, 2048) == (18, 4)
     assert plan(3072, 4096, 4096) == (18, 1)
+    # where the big tile would split K and unsplit 64 x 64 tiles give every
+    # compute unit one or two workgroups, those run (two K groups, 15), up
+    # to K = 4096; at K = 8192 the big tile's many short ranges stay
+    assert plan(512, 2048, 2048) == (15, 1)
+    assert plan(1024, 2048, 1024) == (15, 1)
+    assert plan(2048, 1024, 2048) == (15, 1)
+    assert plan(1024, 1024, 4096) == (15, 1)
+    assert plan(512, 4096, 4096) == (15, 1)
+    assert plan(1024, 2048, 8192) == (17, 8)
+    assert plan(768, 1536, 8192) == (17, 13)
+    # two K groups at two workgroups per compute unit only with K ranges of
+    # 512 or more: shorter ones keep the one-group tile (12)
+    assert plan(640, 3072, 8192) == (15, 1)
+    assert plan(640, 1536, 4096) == (15, 2)
+    assert plan(1536, 768, 128) == (12, 1)
+    assert plan(512, 2560, 256) == (12, 1)
+    assert plan(1024, 640, 512) == (12, 2)
 
 
 def test_fp32_model_of_the_eight_wave_tile(rule):
