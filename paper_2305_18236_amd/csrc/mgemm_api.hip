@@ -352,6 +352,16 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
     // faster (1024 x 2048 x 8192: 277.7 against 294.9).
     const int64_t t64 = tiles(M, N, 64, 64);
     if (s0 > 1 && K <= 4096 && t64 >= cus && t64 <= 2 * cus) return Fp32Plan{3, 1};
+    // Likewise the 128 x 128 tile unsplit (as eight waves, configuration 18)
+    // against the 256 x 256 tile's K ranges, while each compute unit's share
+    // K * tiles / cus stays within 4096 x one tile (us, NN, 17 split ->
+    // 18 unsplit): 4096 x 1024 x 2048 in four ranges 155.8 -> 140.0, 2048 x
+    // 4096 x 1024 in two 160.7 -> 145.9, 2048 x 2048 x 4096 in four 278.5 ->
+    // 272.2, 2048 x 4096 x 2048 in two 282.9 -> 277.8; beyond it the split
+    // wins (2048 x 4096 x 4096: 527.1 against 541.1; 2048 x 2048 x 8192:
+    // 523.9 against 534.5).
+    const int64_t t128 = tiles(M, N, 128, 128);
+    if (pick == 5 && s0 > 1 && t128 >= cus && t128 <= 2 * cus && K * t128 <= 4096 * cus) return Fp32Plan{0, 1};
     if (n * 10 >= rounds * cus * 8) return keep;   // last round at least 80 % full
     Fp32Plan best = keep;
     double best_t = 0.95 * fp32_model_us(pick, M, N, K, s0, cus);

@@ -219,7 +219,7 @@ def test_fp32_round_plan(rule):
     # the 256 x 256 tile runs as its two-staging-set form (17)
     assert plan(8192, 8192, 8192) == (17, 1)
     assert plan(4096, 4096, 4096) == (17, 1)
-    assert plan(2048, 2048, 2048) == (17, 4)
+    assert plan(2048, 2048, 2048) == (18, 1)   # 128 x 128 unsplit, below
     assert plan(4096, 4096, 1024) == (17, 1)
     assert plan(256, 8192, 8192) == (17, 8)
     assert plan(8192, 8192, 256) == (20, 1)   # the 128 x 64 tile over eight waves
@@ -248,6 +248,13 @@ def test_fp32_round_plan(rule):
     assert plan(768, 1536, 8192) == (17, 13)
     # two K groups at two workgroups per compute unit only with K ranges of
     # 512 or more: shorter ones keep the one-group tile (12)
+    # the same for the 128 x 128 tile (18) against split 256 x 256 tiles,
+    # while K * tiles stays within 4096 per compute unit
+    assert plan(4096, 1024, 2048) == (18, 1)
+    assert plan(2048, 4096, 1024) == (18, 1)
+    assert plan(2048, 2048, 4096) == (18, 1)
+    assert plan(2048, 4096, 4096) == (17, 2)
+    assert plan(2048, 2048, 8192) == (17, 4)
     assert plan(640, 3072, 8192) == (15, 1)
     assert plan(640, 1536, 4096) == (15, 2)
     assert plan(1536, 768, 128) == (12, 1)
@@ -257,11 +264,10 @@ def test_fp32_round_plan(rule):
 
 def test_fp32_model_of_the_eight_wave_tile(rule):
     native = rule
-    """The round plan's model charges the 128 x 128 tile configuration 18's
-    measured rate: with the 2048^3 entry out of the way, 2048^3 still plans
-    the 256 x 256 tile in four K ranges (rounds already whole), while the
-    committed table takes configuration 18 unsplit there."""
-    assert (native.mg_tuned_config(0, 2048, 2048, 2048), native.mg_split_count(0, 2048, 2048, 2048)) == (17, 4)
+    """Without the tuning table the rule plans 2048^3 as the committed
+    table does: configuration 18, the 128 x 128 tile over eight waves,
+    unsplit."""
+    assert (native.mg_tuned_config(0, 2048, 2048, 2048), native.mg_split_count(0, 2048, 2048, 2048)) == (18, 1)
     native._load_default_tuning(native.lib())
     assert native.mg_tuned_config(0, 2048, 2048, 2048) == 18
 
