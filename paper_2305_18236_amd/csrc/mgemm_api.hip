@@ -350,8 +350,12 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
     // sixteen 93.2 -> 85.0, 512 x 2048 x 2048 in four of 128 x 128 46.6 ->
     // 45.6; TT alike.  At K = 8192 the many short ranges of the big tile stay
     // faster (1024 x 2048 x 8192: 277.7 against 294.9).
+    // (Both only where the smaller tiles' last round is at least 80 % full:
+    // 3072 x 1664 x 3072, 312 tiles of 128 x 128, ran 407 us unsplit against
+    // 322 us in two K ranges.)
+    auto full = [&](int64_t t) { return t * 10 >= ((t + cus - 1) / cus) * cus * 8; };
     const int64_t t64 = tiles(M, N, 64, 64);
-    if (s0 > 1 && K <= 4096 && t64 >= cus && t64 <= 2 * cus) return Fp32Plan{3, 1};
+    if (s0 > 1 && K <= 4096 && t64 >= cus && t64 <= 2 * cus && full(t64)) return Fp32Plan{3, 1};
     // Likewise the 128 x 128 tile unsplit (as eight waves, configuration 18)
     // against the 256 x 256 tile's K ranges, while each compute unit's share
     // K * tiles / cus stays within 4096 x one tile (us, NN, 17 split ->
@@ -361,7 +365,8 @@ Fp32Plan fp32_plan(int64_t M, int64_t N, int64_t K, int pick, bool split_ok)
     // wins (2048 x 4096 x 4096: 527.1 against 541.1; 2048 x 2048 x 8192:
     // 523.9 against 534.5).
     const int64_t t128 = tiles(M, N, 128, 128);
-    if (pick == 5 && s0 > 1 && t128 >= cus && t128 <= 2 * cus && K * t128 <= 4096 * cus) return Fp32Plan{0, 1};
+    if (pick == 5 && s0 > 1 && t128 >= cus && t128 <= 2 * cus && full(t128) && K * t128 <= 4096 * cus)
+        return Fp32Plan{0, 1};
     if (n * 10 >= rounds * cus * 8) return keep;   // last round at least 80 % full
     Fp32Plan best = keep;
     double best_t = 0.95 * fp32_model_us(pick, M, N, K, s0, cus);

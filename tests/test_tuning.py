@@ -255,6 +255,10 @@ def test_fp32_round_plan(rule):
     assert plan(2048, 2048, 4096) == (18, 1)
     assert plan(2048, 4096, 4096) == (17, 2)
     assert plan(2048, 2048, 8192) == (17, 4)
+    # ... only where the smaller tiles' last round is at least 80 % full
+    assert plan(3072, 1664, 3072) != (18, 1)   # 312 tiles of 128 x 128
+    assert plan(896, 6144, 1536) != (18, 1)    # 336
+    assert plan(1088, 1088, 2048) != (15, 1)   # 289 tiles of 64 x 64
     assert plan(640, 3072, 8192) == (15, 1)
     assert plan(640, 1536, 4096) == (15, 2)
     assert plan(1536, 768, 128) == (12, 1)
