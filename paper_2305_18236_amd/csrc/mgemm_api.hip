@@ -194,10 +194,29 @@ int splits_16bit(int64_t t, int64_t K, int64_t cus)
     return s < 2 ? 1 : int(s);
 }
 
+// The ladder's fill test: enough K ranges for one workgroup per compute
+// unit, rounded up.
+int fill_splits(int64_t t, int64_t K)
+{
+    const int64_t cus = device_cus();
+    if (t <= 0 || t >= cus) return 1;
+    const int64_t s = std::min<int64_t>({(cus + t - 1) / t, K / kMinRange, kMaxSplits});
+    return s < 2 ? 1 : int(s);
+}
+
 int auto_splits(int64_t t, int64_t K)
 {
     const int64_t cus = device_cus();
     if (t <= 0 || t >= cus) return 1;   // no tiles (M or N is 0): nothing to split
+    // Tiles that already keep 84 % of the compute units busy run whole up to
+    // K = 3072: two K ranges would leave as many idle in each of two rounds
+    // and add the reduction (us, two ranges -> one: 7936 x 2048 x 1536 on 248
+    // tiles of 256 x 256 436.2 -> 392.3, 2816 x 5120 x 1536 on 220 431.7 ->
+    // 392.4, 2688 x 5888 x 2048 559.6 -> 515.6, 2944 x 4608 x 3072 795.2 ->
+    // 758.5; 768 x 4992 x 768 on 234 tiles of 128 x 128 71.8 -> 58.2).  With
+    // longer K the reduction weighs less and the split stays (3200 x 4224 x
+    // 8192: 2134.1 against 2209.0 whole).
+    if (K <= 3072 && t * 100 >= 84 * cus) return 1;
     const int64_t s = std::min<int64_t>({(cus + t - 1) / t, K / kMinRange, kMaxSplits});
     return s < 2 ? 1 : int(s);
 }
@@ -272,7 +291,7 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
                 return path == MG_PATH_BF16X3 ? 6 : 11;
             return ladder[i];
         }
-        const int s = split_ok ? auto_splits(n, K) : 1;
+        const int s = split_ok ? fill_splits(n, K) : 1;
         if (n * s < cus) continue;
         // FP32: when this tile needs K ranges as short as kMinRange to fill
         // the GPU and the next smaller tile fills it unsplit, the smaller one

@@ -259,6 +259,11 @@ def test_fp32_round_plan(rule):
     assert plan(3072, 1664, 3072) != (18, 1)   # 312 tiles of 128 x 128
     assert plan(896, 6144, 1536) != (18, 1)    # 336
     assert plan(1088, 1088, 2048) != (15, 1)   # 289 tiles of 64 x 64
+    # tiles that keep 84 % of the compute units busy run whole up to K = 3072
+    assert plan(7936, 2048, 1536) == (17, 1)   # 248 tiles of 256 x 256
+    assert plan(2304, 6912, 768) == (17, 1)    # 243
+    assert plan(768, 4992, 768) == (18, 1)     # 234 tiles of 128 x 128
+    assert plan(3200, 4224, 8192) == (17, 2)   # longer K keeps the split
     assert plan(640, 3072, 8192) == (15, 1)
     assert plan(640, 1536, 4096) == (15, 2)
     assert plan(1536, 768, 128) == (12, 1)
