@@ -263,8 +263,13 @@ def test_fp32_round_plan(rule):
     assert plan(7936, 2048, 1536) == (17, 1)   # 248 tiles of 256 x 256
     assert plan(2304, 6912, 768) == (17, 1)    # 243
     assert plan(768, 4992, 768) == (18, 1)     # 234 tiles of 128 x 128
-    assert plan(3200, 4224, 8192) == (17, 2)   # longer K keeps the split
-    assert plan(640, 3072, 8192) == (15, 1)
+    assert plan(3200, 4224, 8192) != (17, 1)   # longer K: no whole run
+    # the round model decides wherever the last round is under 90 % full,
+    # and weighs plans that keep 80 % of the compute units busy
+    assert plan(3200, 4224, 8192) == (18, 4)   # 442 workgroups of 256 x 256: 86 %
+    assert plan(3584, 3712, 3072) == (12, 1)   # 420: 82 %
+    assert plan(7552, 1664, 8192) == (18, 1)   # 207 tiles of 128 x 128: 81 %
+    assert plan(640, 3072, 8192) == (18, 2)   # 240 workgroups: 283.2 us against 292.4 for (15, 1)
     assert plan(640, 1536, 4096) == (15, 2)
     assert plan(1536, 768, 128) == (12, 1)
     assert plan(512, 2560, 256) == (12, 1)
