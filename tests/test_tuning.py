@@ -270,7 +270,7 @@ def test_fp32_round_plan(rule):
     assert plan(3584, 3712, 3072) == (12, 1)   # 420: 82 %
     assert plan(7552, 1664, 8192) == (18, 1)   # 207 tiles of 128 x 128: 81 %
     assert plan(640, 3072, 8192) == (18, 2)   # 240 workgroups: 283.2 us against 292.4 for (15, 1)
-    assert plan(640, 1536, 4096) == (15, 2)
+    assert plan(640, 1536, 4096) == (15, 1)   # 240 tiles, 94 %: 84.5 us against 83.3 in two ranges
     assert plan(1536, 768, 128) == (12, 1)
     assert plan(512, 2560, 256) == (12, 1)
     assert plan(1024, 640, 512) == (12, 2)
