@@ -278,8 +278,23 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // against 237.5).  The 128 x 128 tile itself keeps its split
             // against the 64 x 64 one (bf16x3 1024^3: 25.0 us in four K
             // ranges, 32.0 us unsplit on 64 x 64 tiles).
+            // Where the split's K ranges are 512 deep or less it does so
+            // once the 128 x 128 tiles keep three quarters of the compute
+            // units busy (us, plan -> 10 unsplit: BF16 3712 x 896 x 1024 on
+            // 203 tiles 40.8 -> 27.8, 768 x 4992 x 768 on 234 37.9 -> 25.0;
+            // bf16x3 50.3 -> 41.1 and 48.0 -> 35.9; on 26 random shapes the
+            // step gained 22-52 % with 256-deep ranges and lost up to 11 %
+            // with ranges of 1536 and more).  And unsplit
+            // 256 x 256 tiles that spill a second round under a quarter full
+            // give way too (BF16 4480 x 3840 x 256, 270 tiles: 44.8 -> 38.0,
+            // 6144 x 3328 x 8192, 312 tiles: 448.3 -> 413.6; bf16x3 67.3 ->
+            // 50.9 and 1086.7 -> 956.5; 54 random shapes of both paths: 12 %
+            // faster in geometric mean, none slower by over 3 %).
+            const int64_t n128 = tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn);
             if (i == 0 && s16 > 1 && (path != MG_PATH_BF16X3 || K / s16 < 2048) &&
-                tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn) >= cus)
+                (n128 >= cus || (n128 * 4 >= cus * 3 && K / s16 <= 512)))
+                return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
+            if (i == 0 && s16 == 1 && n > cus && n < 2 * cus && (n - cus) * 4 < cus)
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
             // BF16 and FP16 run that tile over sixteen 64 x 64 waves (11,
             // four per SIMD, bit-identical to 6): end to end, us, 6 -> 11:

@@ -308,6 +308,22 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
     # 256 rows: no planes; 128 x 128 tiles (2 x 64 = 128) do not fill the
     # compute units, so the ladder's split stays
     assert native.mg_tuned_config(2, 256, 8192, 8192) == 1
+    # K ranges of 512 or less: the step down already where 128 x 128 tiles
+    # keep three quarters of the compute units busy (203-234 tiles)
+    for path in (1, 2):
+        for shape in ((3712, 896, 1024), (768, 4992, 768), (2048, 1664, 768)):
+            assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (10, 1), \
+                (path, shape)
+    # longer ranges keep the split there
+    assert native.mg_split_count(2, 1792, 1920, 8192) == 4
+    assert native.mg_tuned_config(2, 1792, 1920, 8192) == 11
+    # unsplit 256 x 256 tiles spilling a second round under a quarter full
+    # (270 and 312 tiles) step down too; 576 tiles (6144^2, a quarter) stay
+    for path in (1, 2):
+        for shape in ((4480, 3840, 256), (6144, 3328, 8192)):
+            assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (10, 1), \
+                (path, shape)
+    assert native.mg_tuned_config(2, 6144, 6144, 2048) == 11
 
 
 def test_sixteen_bit_split_rule(rule):
