@@ -485,7 +485,14 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // faster than the interleaved pack (GEMM only, us, 6 -> 10: 2048^3
         // 17.7 -> 14.8, 2560^3 27.1 -> 25.0, 4096 x 2048 x 2048 24.6 -> 22.3,
         // 1536^3 14.1 -> 11.4).
-        if (tiles(M, N, 256, 256) * 2 > cus) return 7;
+        // 256 x 256 tiles that spill a second round under a quarter full
+        // give way to the 128 x 128 tile (us, 7 -> 10: 4480 x 3840 x 256 on
+        // 270 tiles 46.5 -> 36.4, 4352 x 4096 x 2048 on 272 94.4 -> 77.3,
+        // 4608 x 4096 x 4096 on 288 148.5 -> 126.2, 6144 x 3328 x 8192 on
+        // 312 292.0 -> 274.3).
+        const int64_t n256 = tiles(M, N, 256, 256);
+        if (n256 > cus && n256 < 2 * cus && (n256 - cus) * 4 < cus) return 10;
+        if (n256 * 2 > cus) return 7;
         if (tiles(M, N, 128, 128) >= 128) return 10;
         return 3;
     }
@@ -502,7 +509,12 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // The 256 x 256 tile runs over sixteen 64 x 64 waves (7): GEMM only,
         // us, 5 -> 7: 8192^3 479.6 -> 473.0, 6144^3 245.9 -> 236.2, 4096^3
         // 66.6 -> 65.8.
-        if (tiles(M, N, 256, 256) * 2 > cus) return 7;
+        // The same step down as FP8 (us, 7 -> 6: 4480 x 3840 x 256 34.0 ->
+        // 25.3, 4352 x 4096 x 2048 77.2 -> 69.7, 4608 x 4096 x 4096 122.6 ->
+        // 109.4, 6144 x 3328 x 8192 222.2 -> 205.9).
+        const int64_t n256 = tiles(M, N, 256, 256);
+        if (n256 > cus && n256 < 2 * cus && (n256 - cus) * 4 < cus) return 6;
+        if (n256 * 2 > cus) return 7;
         if (tiles(M, N, 128, 128) >= 128) return 6;
         return 2;
     }

@@ -326,6 +326,19 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
     assert native.mg_tuned_config(2, 6144, 6144, 2048) == 11
 
 
+def test_eight_bit_step_down_from_a_spilled_round(rule):
+    native = rule
+    """FP8 and INT8: 256 x 256 tiles that spill a second round under a
+    quarter full (257-319 tiles) give way to the 128 x 128 direct tile;
+    whole rounds and fuller second rounds keep the big tile."""
+    for shape in ((4480, 3840, 256), (4352, 4096, 2048), (6144, 3328, 8192)):
+        assert native.mg_tuned_config(3, *shape) == 10, shape
+        assert native.mg_tuned_config(5, *shape) == 6, shape
+    for shape in ((4096, 4096, 4096), (6144, 6144, 2048)):
+        assert native.mg_tuned_config(3, *shape) == 7, shape
+        assert native.mg_tuned_config(5, *shape) == 7, shape
+
+
 def test_sixteen_bit_split_rule(rule):
     native = rule
     """16-bit paths split K into as many ranges as fit one round of
