@@ -262,8 +262,14 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // 4096 x 2048 x 8192 283 -> 347, 2048 x 8192 x 2048 342 -> 390,
             // 4096^3 360 -> 409; losses at 2048^3 235 -> 224, 2048 x 2048 x 8192
             // 327 -> 312, 1024 x 8192 x 4096 327 -> 305; ties at 16384 x 1024 x
-            // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separates them:
-            // M N >= 1250 (M + N) for bf16x3.
+            // 4096 and 8192 x 1024 x 8192.  1/M + 1/N <= 0.0008 separated them
+            // then.  With the faster direct-copy kernels the bound moved:
+            // M N >= 1050 (M + N) for bf16x3 (22 random shapes between the
+            // two bounds, us, in-kernel split -> planes: 5504 x 1536 x 4096
+            // 345.6 -> 253.9, 1536 x 5760 x 1024 102.4 -> 78.7, 2688 x 2176 x
+            // 8192 396.6 -> 319.3; 4-36 % faster, 19 % in geometric mean).
+            // At 900 (M + N) the earlier losses return (2048 x 2048 x 8192:
+            // 212.8 against 202.5, 1024 x 8192 x 4096: 219.9 against 206.9).
             const int s16 = split_ok ? splits_16bit(n, K, cus) : 1;
             if (n * s16 * 2 < cus) continue;
             // The 256 x 256 tile, when it needs a K split, gives way to the
@@ -302,7 +308,7 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // 142.3 -> 141.0; FP16 8192^3 1066.6 -> 1037.5.  bf16x3 keeps
             // eight (8192^3 2454 against 2482 with sixteen).
             if (ladder[i] == 1 && uses_planes(path, 6, M, N, K) &&
-                (path != MG_PATH_BF16X3 || M * N >= 1250 * (M + N)))
+                (path != MG_PATH_BF16X3 || M * N >= 1050 * (M + N)))
                 return path == MG_PATH_BF16X3 ? 6 : 11;
             return ladder[i];
         }

@@ -326,6 +326,16 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
     assert native.mg_tuned_config(2, 6144, 6144, 2048) == 11
 
 
+def test_bf16x3_planes_bound(rule):
+    native = rule
+    """bf16x3 runs the 256 x 256 tile on pre-packed planes (6) once
+    M N >= 1050 (M + N); below that its in-kernel form (1)."""
+    assert native.mg_tuned_config(1, 5504, 1536, 4096) == 6     # 1201 (M + N)
+    assert native.mg_tuned_config(1, 1536, 5760, 1024) == 6     # 1213
+    assert native.mg_tuned_config(1, 2048, 2048, 8192) == 1     # 1024
+    assert native.mg_tuned_config(1, 1024, 8192, 4096) == 1     # 910
+
+
 def test_eight_bit_step_down_from_a_spilled_round(rule):
     native = rule
     """FP8 and INT8: 256 x 256 tiles that spill a second round under a
