@@ -272,6 +272,21 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // 212.8 against 202.5, 1024 x 8192 x 4096: 219.9 against 206.9).
             const int s16 = split_ok ? splits_16bit(n, K, cus) : 1;
             if (n * s16 * 2 < cus) continue;
+            // BF16 and FP16: a tile that needs a K split into ranges of 384
+            // or less (K up to 2048, M and N at least 512) gives way to the
+            // 64 x 64 tile if that one alone gives each compute unit one or
+            // two workgroups.  On 16 random shapes of that kind it was 9-52 %
+            // faster (us, plan -> 4 unsplit: 2176 x 768 x 512 25.2 -> 16.1,
+            // 2048 x 1024 x 1536 in six ranges 1.35x, 1280 x 1280 x 768
+            // 1.25x).  Outside it the step lost: a side of 256 or 384 (the
+            // 256 x 256 in-kernel tile split 7-12 ways ran 2-3x faster),
+            // longer ranges (up to 9 % slower at 512 deep).  bf16x3's three
+            // products per step keep the larger tiles ahead (512 x 2688 x
+            // 768: 24.7 us split against 31.0).
+            const int64_t n64 = tiles(M, N, 64, 64);
+            if (i < 2 && s16 > 1 && (path == MG_PATH_BF16 || path == MG_PATH_FP16) && n64 >= cus &&
+                n64 <= 2 * cus && std::min(M, N) >= 512 && K <= 2048 && K / s16 <= 384)
+                return ladder[2];
             // The 256 x 256 tile, when it needs a K split, gives way to the
             // 128 x 128 tile if that one fills the GPU unsplit: on pre-packed
             // planes as eight waves fed by direct copies (10), else in its

@@ -326,6 +326,21 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
     assert native.mg_tuned_config(2, 6144, 6144, 2048) == 11
 
 
+def test_sixteen_bit_short_k_ranges_take_64_tiles(rule):
+    native = rule
+    """BF16 and FP16: where the ladder's tile needs K ranges of 384 or less
+    (K up to 2048, both sides at least 512) and 64 x 64 tiles alone give each
+    compute unit one or two workgroups, those run unsplit (4); bf16x3 and
+    the narrow or long-K shapes keep the split."""
+    for path in (2, 4):
+        for shape in ((2176, 768, 512), (1280, 1280, 768), (2048, 1024, 1536)):
+            assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (4, 1), \
+                (path, shape)
+    assert native.mg_tuned_config(1, 2176, 768, 512) != 4
+    assert native.mg_tuned_config(2, 256, 4480, 3072) != 4      # a side of 256
+    assert native.mg_tuned_config(2, 512, 2176, 1536) != 4      # 512-deep ranges
+
+
 def test_bf16x3_planes_bound(rule):
     native = rule
     """bf16x3 runs the 256 x 256 tile on pre-packed planes (6) once
