@@ -511,9 +511,16 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // 270 tiles 46.5 -> 36.4, 4352 x 4096 x 2048 on 272 94.4 -> 77.3,
         // 4608 x 4096 x 4096 on 288 148.5 -> 126.2, 6144 x 3328 x 8192 on
         // 312 292.0 -> 274.3).
+        // The 256 x 256 tile runs over sixteen 64 x 64 waves (11): on 22
+        // shapes off the tuned table with 100-1024 tiles it was ahead of the
+        // eight-wave form in 21, by up to 6.8 %, and 0.7 % behind in one
+        // (GEMM only, us, 7 -> 11: 8192 x 8192 x 2048 252.5 -> 236.3, 6144
+        // x 7168 x 2048 168.5 -> 163.0, 7168 x 7168 x 4096 331.2 -> 320.0,
+        // 2816 x 3584 x 2048 51.7 -> 49.2).  The tuned table keeps 7 where
+        // it measured that ahead (4096^3, 8192^3).
         const int64_t n256 = tiles(M, N, 256, 256);
         if (n256 > cus && n256 < 2 * cus && (n256 - cus) * 4 < cus) return 10;
-        if (n256 * 2 > cus) return 7;
+        if (n256 * 2 > cus) return 11;
         if (tiles(M, N, 128, 128) >= 128) return 10;
         return 3;
     }
