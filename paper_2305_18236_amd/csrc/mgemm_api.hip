@@ -299,7 +299,9 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // against 237.5).  The 128 x 128 tile itself keeps its split
             // against the 64 x 64 one (bf16x3 1024^3: 25.0 us in four K
             // ranges, 32.0 us unsplit on 64 x 64 tiles).
-            // Where the split's K ranges are 512 deep or less it does so
+            // Where the split's K ranges are 512 deep or less (BF16 and
+            // FP16: 1024; 24 random shapes between the two bounds ran 1-31 %
+            // faster, 13 % in geometric mean) it does so
             // once the 128 x 128 tiles keep three quarters of the compute
             // units busy (us, plan -> 10 unsplit: BF16 3712 x 896 x 1024 on
             // 203 tiles 40.8 -> 27.8, 768 x 4992 x 768 on 234 37.9 -> 25.0;
@@ -313,7 +315,7 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // faster in geometric mean, none slower by over 3 %).
             const int64_t n128 = tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn);
             if (i == 0 && s16 > 1 && (path != MG_PATH_BF16X3 || K / s16 < 2048) &&
-                (n128 >= cus || (n128 * 4 >= cus * 3 && K / s16 <= 512)))
+                (n128 >= cus || (n128 * 4 >= cus * 3 && K / s16 <= (path == MG_PATH_BF16X3 ? 512 : 1024))))
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
             if (i == 0 && s16 == 1 && n > cus && n < 2 * cus && (n - cus) * 4 < cus)
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];

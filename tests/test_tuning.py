@@ -314,6 +314,11 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
         for shape in ((3712, 896, 1024), (768, 4992, 768), (2048, 1664, 768)):
             assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (10, 1), \
                 (path, shape)
+    # BF16 and FP16 also with ranges up to 1024 deep, bf16x3 not
+    for path in (2, 4):
+        assert (native.mg_tuned_config(path, 3584, 1152, 2048), native.mg_split_count(path, 3584, 1152, 2048)) == (10, 1)
+        assert (native.mg_tuned_config(path, 2560, 1280, 3072), native.mg_split_count(path, 2560, 1280, 3072)) == (10, 1)
+    assert native.mg_tuned_config(1, 2560, 1280, 3072) != 10
     # longer ranges keep the split there
     assert native.mg_split_count(2, 1792, 1920, 8192) == 4
     assert native.mg_tuned_config(2, 1792, 1920, 8192) == 11
