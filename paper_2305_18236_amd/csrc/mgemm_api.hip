@@ -312,12 +312,16 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // give way too (BF16 4480 x 3840 x 256, 270 tiles: 44.8 -> 38.0,
             // 6144 x 3328 x 8192, 312 tiles: 448.3 -> 413.6; bf16x3 67.3 ->
             // 50.9 and 1086.7 -> 956.5; 54 random shapes of both paths: 12 %
-            // faster in geometric mean, none slower by over 3 %).
+            // faster in geometric mean, none slower by over 3 %).  bf16x3
+            // steps down up to a third full (26 random shapes with 320-341
+            // tiles: 12 % faster in geometric mean, 2560 x 8192 x 512 101.8
+            // -> 81.2, 4096 x 5120 x 4096 548.5 -> 462.8; none slower by over
+            // 2 %).
             const int64_t n128 = tiles(M, N, t.cfgs[ladder[1]].bm, t.cfgs[ladder[1]].bn);
             if (i == 0 && s16 > 1 && (path != MG_PATH_BF16X3 || K / s16 < 2048) &&
                 (n128 >= cus || (n128 * 4 >= cus * 3 && K / s16 <= (path == MG_PATH_BF16X3 ? 512 : 1024))))
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
-            if (i == 0 && s16 == 1 && n > cus && n < 2 * cus && (n - cus) * 4 < cus)
+            if (i == 0 && s16 == 1 && n > cus && n < 2 * cus && (n - cus) * (path == MG_PATH_BF16X3 ? 3 : 4) < cus)
                 return uses_planes(path, 10, M, N, K) ? 10 : ladder[1];
             // BF16 and FP16 run that tile over sixteen 64 x 64 waves (11,
             // four per SIMD, bit-identical to 6): end to end, us, 6 -> 11:

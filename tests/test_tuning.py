@@ -329,6 +329,11 @@ def test_sixteen_bit_ladder_steps_down_from_split_k(rule):
             assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (10, 1), \
                 (path, shape)
     assert native.mg_tuned_config(2, 6144, 6144, 2048) == 11
+    # bf16x3 steps down up to a third full (4096 x 5120: 320 tiles, 25 %;
+    # 6144 x 3456: 336, 31 %); BF16 keeps the big tile there
+    for shape in ((4096, 5120, 4096), (6144, 3456, 768)):
+        assert native.mg_tuned_config(1, *shape) == 10, shape
+    assert native.mg_tuned_config(2, 6144, 3456, 768) == 11
 
 
 def test_sixteen_bit_short_k_ranges_take_64_tiles(rule):
