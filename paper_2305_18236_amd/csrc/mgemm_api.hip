@@ -524,8 +524,11 @@ int choose_config(int path, int64_t M, int64_t N, int64_t K, bool split_ok)
         // x 7168 x 2048 168.5 -> 163.0, 7168 x 7168 x 4096 331.2 -> 320.0,
         // 2816 x 3584 x 2048 51.7 -> 49.2).  The tuned table keeps 7 where
         // it measured that ahead (4096^3, 8192^3).
+        // Up to a third full, as bf16x3: 12 random shapes with 320-341
+        // tiles all ran faster on the 128 x 128 tile (0-15 %, 6 % in
+        // geometric mean; INT8 lost up to 10 % there and keeps a quarter).
         const int64_t n256 = tiles(M, N, 256, 256);
-        if (n256 > cus && n256 < 2 * cus && (n256 - cus) * 4 < cus) return 10;
+        if (n256 > cus && n256 < 2 * cus && (n256 - cus) * 3 < cus) return 10;
         if (n256 * 2 > cus) return 11;
         if (tiles(M, N, 128, 128) >= 128) return 10;
         return 3;

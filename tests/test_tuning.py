@@ -369,6 +369,9 @@ def test_eight_bit_step_down_from_a_spilled_round(rule):
     for shape in ((4480, 3840, 256), (4352, 4096, 2048), (6144, 3328, 8192)):
         assert native.mg_tuned_config(3, *shape) == 10, shape
         assert native.mg_tuned_config(5, *shape) == 6, shape
+    # FP8 up to a third full (330 tiles), INT8 a quarter
+    assert native.mg_tuned_config(3, 3840, 5504, 1024) == 10
+    assert native.mg_tuned_config(5, 3840, 5504, 1024) == 7
     for shape in ((4096, 4096, 4096), (6144, 6144, 2048)):
         assert native.mg_tuned_config(3, *shape) == 11, shape   # FP8: sixteen waves by rule
         assert native.mg_tuned_config(5, *shape) == 7, shape
