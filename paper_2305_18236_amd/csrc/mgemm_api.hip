@@ -281,11 +281,13 @@ int ladder_choice(int path, int64_t M, int64_t N, int64_t K, int64_t cus, bool s
             // 1.25x).  Outside it the step lost: a side of 256 or 384 (the
             // 256 x 256 in-kernel tile split 7-12 ways ran 2-3x faster),
             // longer ranges (up to 9 % slower at 512 deep).  bf16x3's three
-            // products per step keep the larger tiles ahead (512 x 2688 x
-            // 768: 24.7 us split against 31.0).
+            // products per step keep the larger tiles ahead from K = 768
+            // (512 x 2688 x 768: 24.7 us split against 31.0); up to K = 512
+            // it steps down too (8 random shapes: 12 % faster in geometric
+            // mean, 3328 x 512 x 512 25.2 -> 21.2).
             const int64_t n64 = tiles(M, N, 64, 64);
-            if (i < 2 && s16 > 1 && (path == MG_PATH_BF16 || path == MG_PATH_FP16) && n64 >= cus &&
-                n64 <= 2 * cus && std::min(M, N) >= 512 && K <= 2048 && K / s16 <= 384)
+            if (i < 2 && s16 > 1 && n64 >= cus && n64 <= 2 * cus && std::min(M, N) >= 512 &&
+                ((path == MG_PATH_BF16 || path == MG_PATH_FP16) ? K <= 2048 && K / s16 <= 384 : K <= 512))
                 return ladder[2];
             // The 256 x 256 tile, when it needs a K split, gives way to the
             // 128 x 128 tile if that one fills the GPU unsplit: on pre-packed

@@ -340,13 +340,14 @@ def test_sixteen_bit_short_k_ranges_take_64_tiles(rule):
     native = rule
     """BF16 and FP16: where the ladder's tile needs K ranges of 384 or less
     (K up to 2048, both sides at least 512) and 64 x 64 tiles alone give each
-    compute unit one or two workgroups, those run unsplit (4); bf16x3 and
-    the narrow or long-K shapes keep the split."""
+    compute unit one or two workgroups, those run unsplit (4); bf16x3 only
+    up to K = 512; the narrow or long-K shapes keep the split."""
     for path in (2, 4):
         for shape in ((2176, 768, 512), (1280, 1280, 768), (2048, 1024, 1536)):
             assert (native.mg_tuned_config(path, *shape), native.mg_split_count(path, *shape)) == (4, 1), \
                 (path, shape)
-    assert native.mg_tuned_config(1, 2176, 768, 512) != 4
+    assert (native.mg_tuned_config(1, 3328, 512, 512), native.mg_split_count(1, 3328, 512, 512)) == (4, 1)
+    assert native.mg_tuned_config(1, 512, 2688, 768) != 4       # bf16x3 from K = 768
     assert native.mg_tuned_config(2, 256, 4480, 3072) != 4      # a side of 256
     assert native.mg_tuned_config(2, 512, 2176, 1536) != 4      # 512-deep ranges
 
